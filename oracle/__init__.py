@@ -1,0 +1,7 @@
+"""FP64 CPU oracle for lattice ITC (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package; the product path must never route through it.
+"""
+from .itc_oracle import *  # noqa: F401,F403
+from .itc_oracle import __all__  # noqa: F401
