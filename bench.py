@@ -1,0 +1,203 @@
+"""Benchmark: images/s to the converged codebook, batched vs per-image, with the
+convolution's roofline and the FP64 oracle timed beside it.
+
+Default workload: the batch of 1,400 star silhouettes (W 128..1024 x H 128..768,
+binary uint8, M in 10..200, sigma in {2, 4, 8}, 100 sweeps, FP32), inputs
+resident in HBM. One step = batched convolution maps of every image + fit of
+every image + D at its final codebook, replayed from a HIP graph.
+
+Prints one JSON line (rank 0). Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "images/sec to converged codebook (batched vs per-image); conv HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+# FP32 FMA without packed instructions: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--images", type=int, default=1400, help="silhouettes in the batch")
+    p.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle leg")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-per-image", action="store_true")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(images would shard across GPUs with no communication); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1310_7114_amd import itc, synth
+
+    itc.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    cases = synth.config3_cases(args.images)
+    print(f"[bench] generated {len(cases)} silhouettes in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    n = len(cases)
+    npx = int(sum(c.img.size for c in cases))
+    plan = itc.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
+                         [c.sigma for c in cases], [c.iters for c in cases], device=dev)
+    w0 = plan.pack_codebooks([c.w0 for c in cases], device=dev)
+    w = torch.empty_like(w0)
+    sx = torch.empty(n, dtype=torch.float64, device=dev)
+    dd = torch.empty(n, dtype=torch.float64, device=dev)
+    done = torch.empty(n, dtype=torch.int32, device=dev)
+
+    # ---------------- batched step captured in a HIP graph ----------------
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(1, args.warmup)):
+            plan.run(w0, w, sx, dd, done)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(w0, w, sx, dd, done)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    print("[bench] warm-up done; timing batched graph replays", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t) / args.steps
+    assert bool(torch.all(done == 100)) and bool(torch.all(torch.isfinite(dd)))
+
+    # ---------------- per-phase timing with events on the launch stream ----------------
+    cur = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    conv_ms, fit_ms = [], []
+    for _ in range(args.steps):
+        ev[0].record(cur)
+        plan.precompute()
+        ev[1].record(cur)
+        plan.fit(w0, w, sx, dd, done)
+        ev[2].record(cur)
+        torch.cuda.synchronize()
+        conv_ms.append(ev[0].elapsed_time(ev[1]))
+        fit_ms.append(ev[1].elapsed_time(ev[2]))
+    conv_s = float(np.mean(conv_ms)) / 1e3
+    fit_s = float(np.mean(fit_ms)) / 1e3
+
+    # algorithmic work of the convolution: 1 B in + 3 x 4 B out per pixel;
+    # 5 filters x (2R+1) taps FMA per pixel (2 flop each)
+    conv_bytes = 13.0 * npx
+    conv_flops = float(sum(2.0 * 5 * (2 * c.R + 1) * c.img.size for c in cases))
+    conv_gbs = conv_bytes / conv_s / 1e9
+    conv_tfs = conv_flops / conv_s / 1e12
+
+    # ---------------- per-image loop (same kernels, one image at a time) ----------------
+    per_image = None
+    if not args.no_per_image:
+        maps = [plan.maps_of(i) for i in range(n)]
+        ws = [plan.unpack(w0, i) for i in range(n)]
+        outs = [plan.unpack(w, i) for i in range(n)]
+        imgs = [plan.weights[int(plan.weight_off[i]): int(plan.weight_off[i]) + cases[i].img.size]
+                .view(cases[i].img.shape) for i in range(n)]
+        dtr = [torch.empty(c.iters + 1, dtype=torch.float64, device=dev) for c in cases]
+        dn = torch.empty(n, dtype=torch.int32, device=dev)
+
+        def loop():
+            for i, c in enumerate(cases):
+                itc.precompute(imgs[i], c.sigma, scale=c.scale, out=maps[i])
+                lib = itc.load()
+                st = lib.itc_lattice_fit(itc.ctypes.byref(maps[i].desc), itc._ptr(maps[i].buf),
+                                         itc._ptr(maps[i].s_x), c.M, itc._ptr(ws[i]), c.iters, -1.0,
+                                         itc._ptr(outs[i]), itc._ptr(dtr[i]), itc._ptr(dn[i:i + 1]),
+                                         itc._stream())
+                itc._check(st)
+
+        with torch.cuda.stream(s):
+            loop()
+        torch.cuda.synchronize()
+        pg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(pg):
+            loop()
+        pg.replay()
+        torch.cuda.synchronize()
+        reps = max(1, min(3, args.steps))
+        t = time.perf_counter()
+        for _ in range(reps):
+            pg.replay()
+        torch.cuda.synchronize()
+        pi_s = (time.perf_counter() - t) / reps
+        per_image = {"value": n / pi_s, "unit": "images/s", "ms_per_pass": pi_s * 1e3,
+                     "launches": "precompute (2 kernels) + fit (1 kernel) per image, one stream, HIP graph"}
+        print(f"[bench] per-image loop {pi_s * 1e3:.1f} ms per pass", file=sys.stderr, flush=True)
+
+    # ---------------- oracle on the host cores ----------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t = time.perf_counter()
+            k = 0
+            while k < n and time.perf_counter() - t < args.cpu_seconds:
+                c = cases[k]
+                O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters)
+                k += 1
+            el = time.perf_counter() - t
+        cpu = {"value": k / el, "unit": "images/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {k} of the {n} silhouettes (same sizes, M, sigma, 100 sweeps), "
+                         f"FP64 NumPy lattice variant, {el:.1f}s"}
+
+    value = n / step_s
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"silhouettes-{n}: binary star polygons, W 128..1024 x H 128..768, "
+                               f"M 10..200, sigma 2/4/8, 100 sweeps, batched persistent + HIP graph",
+                   "images": n, "pixels": npx, "iters": 100},
+        "phases_ms": {"conv": conv_s * 1e3, "fit_and_divergence": fit_s * 1e3},
+        "per_image": per_image,
+        "batched_over_per_image": (value / per_image["value"]) if per_image else None,
+        "conv_hbm": {"achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": conv_gbs / HBM_PEAK_GBS, "bytes_per_px": 13},
+        "roofline": {"bound": "alu", "achieved": conv_tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": conv_tfs / VALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "convolution maps (per-radius-class persistent launches)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

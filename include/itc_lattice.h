@@ -1,0 +1,216 @@
+/*
+ * itc_lattice.h -- C ABI of the MI355X (gfx950) lattice ITC library.
+ *
+ * Information theoretic clustering (Bauckhage & Kersting, "Efficient
+ * Information Theoretic Clustering on Discrete Lattices") places M codevectors
+ * w_k on a weighted lattice image I by minimising the Cauchy-Schwarz
+ * divergence of eq. (1) with the fixed-point update of eq. (4). On a lattice
+ * the data sums of eq. (4) are Gaussian convolutions (Section 3.1; weighted
+ * data, Section 5). This library computes
+ *
+ *   A(x)   = sum_y I(y)             g(x - y)      (density map, "P = X * G")
+ *   M_u(x) = sum_y I(y) (x_u - y_u) g(x - y)      (pixel-centred moments; the
+ *   M_v(x) = sum_y I(y) (x_v - y_v) g(x - y)       u*I, v*I convolutions are
+ *                                                   B = x A - M)
+ *   S_X    = sum_x I(x) A(x)
+ *
+ * with g(d) = exp(-|d|^2 / (2 sigma^2)) on the square window |d_u|,|d_v| <= R,
+ * and iterates, for every codevector k (Jacobi order, all from W_old):
+ *
+ *   A_k = A(w_k),  g_k = (B - A w)(w_k)              (bilinear map reads)
+ *   C_k = sum_j g(w_j - w_k),  E_k = sum_j g(w_j - w_k)(w_j - w_k)   (all j)
+ *   c   = S_XW / S_W,  S_XW = sum_k A_k,  S_W = sum_k C_k
+ *   w_k <- w_k + (g_k - c E_k) / A_k       (w_k frozen when A_k == 0)
+ *   D   = log S_W + log S_X - 2 log S_XW    (eq. (1) with tau = rho = sigma)
+ *
+ * This is eq. (4) with one kernel width (xi = omega = sigma/sqrt 2) and the
+ * Parzen normalisations cancelled; D equals eq. (1) exactly in that reading.
+ *
+ * Coordinates: u = row, v = column, 0-based, pixel centres at integers.
+ * Codebooks are arrays of M (u, v) pairs in the real type.
+ *
+ * Conventions for every entry point:
+ *  - Buffers are device memory unless marked "host". The caller owns all of
+ *    them; the library allocates nothing per call (plans own their device
+ *    descriptor arrays, allocated once by itc_lattice_plan_create).
+ *  - `stream` is a hipStream_t (NULL = the null stream). Calls enqueue work
+ *    and return; results are valid after the stream is synchronised.
+ *  - All argument checks run on the host before anything is enqueued. On an
+ *    error nothing is enqueued, outputs are untouched and itc_last_error()
+ *    gives the reason. No C++ exception crosses this boundary.
+ *  - Checks that fail return ITC_E_NULL (null pointer), ITC_E_ARG (a size,
+ *    width or count out of range), ITC_E_UNSUPPORTED (valid but beyond what
+ *    the kernels are built for: R > 32 for FP32, R > 16 for FP64, M > 1024),
+ *    ITC_E_DEVICE (a HIP launch or runtime error).
+ */
+#ifndef ITC_LATTICE_H
+#define ITC_LATTICE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ITC_OK = 0,
+  ITC_E_NULL = 1,
+  ITC_E_ARG = 2,
+  ITC_E_UNSUPPORTED = 3,
+  ITC_E_DEVICE = 4
+} itc_status;
+
+typedef enum { ITC_U8 = 0, ITC_F32 = 1, ITC_F64 = 2 } itc_dtype;
+
+/* Maximum supported sizes (ITC_E_UNSUPPORTED beyond them). */
+#define ITC_MAX_RADIUS_F32 32
+#define ITC_MAX_RADIUS_F64 16
+#define ITC_MAX_CODEVECTORS 1024
+
+/*
+ * One lattice problem. The weight image (Section 3.2 binary image, or
+ * Section 5 per-pixel weights) is `height` rows of `width` stored values with
+ * row pitch `pitch` elements; the weight is h = weight_scale * stored
+ * (1 for 0/1 binary images, 1/255 for gray values g/255). `sigma` is the
+ * Gaussian width in pixels (Section 2.1 with tau = rho = sigma); `radius` is
+ * the truncation R of the window (Section 3.1 finite masks), 0 selecting
+ * ceil(3 sigma). `real_dtype` selects FP32 or FP64 maps, codebooks and
+ * arithmetic; S_X, S_XW, S_W and D are always accumulated in FP64.
+ */
+typedef struct {
+  int32_t height;
+  int32_t width;
+  int64_t pitch;
+  int32_t weight_dtype; /* itc_dtype of the stored weights */
+  int32_t real_dtype;   /* ITC_F32 or ITC_F64 */
+  double weight_scale;
+  double sigma;
+  int32_t radius;
+  int32_t reserved; /* must be 0 */
+} itc_lattice_desc;
+
+/* Effective truncation radius of `d` (radius, or ceil(3 sigma) when 0); -1 if invalid. */
+int32_t itc_lattice_radius(const itc_lattice_desc* d);
+
+/* Elements per map row (width rounded up to a multiple of 64); -1 if invalid. */
+int64_t itc_lattice_map_pitch(const itc_lattice_desc* d);
+
+/*
+ * Bytes of the maps buffer for `d`, 0 if `d` is invalid. Layout (all in the
+ * real type unless stated): plane A, then plane M_u, then plane M_v, each
+ * height x map_pitch row-major; then a trailer of ceil(width/64) x
+ * ceil(height/4) FP64 partial sums of S_X (library-internal). The size is a
+ * multiple of 256 bytes; the buffer must be 256-byte aligned.
+ */
+size_t itc_lattice_maps_bytes(const itc_lattice_desc* d);
+
+/*
+ * Section 3.1 / Algorithm 1 "compute P once": the convolution maps of the
+ * weight image and S_X. `weights` points at the stored image (layout in `d`),
+ * `maps` at itc_lattice_maps_bytes(d) bytes (written), `s_x` at one double
+ * (written). Map columns beyond `width` inside the pitch are left untouched.
+ */
+itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights, void* maps,
+                                  double* s_x, void* stream);
+
+/*
+ * Algorithm 1's loop: `iters` Jacobi sweeps of eq. (4) from `w_init`
+ * ([M][2], real type) with the data terms read from `maps` (as written by
+ * itc_lattice_precompute for the same `d`). Stops early after a sweep whose
+ * largest codevector step max_k ||w_k^new - w_k||_2 is <= theta (theta < 0:
+ * never). Writes the final codebook to `w_out` ([M][2]; may alias w_init).
+ * Optional outputs (NULL to skip): `d_trace` ([iters+1] doubles; entry t is D
+ * at the codebook after t sweeps, entries past the stop are untouched),
+ * `iters_done` (one int32, sweeps performed). `s_x` (from precompute) is
+ * required when d_trace is requested, else may be NULL. iters == 0 copies
+ * w_init to w_out and, when asked, writes D(w_init) to d_trace[0].
+ * 1 <= M <= ITC_MAX_CODEVECTORS.
+ */
+itc_status itc_lattice_fit(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
+                           const void* w_init, int32_t iters, double theta, void* w_out,
+                           double* d_trace, int32_t* iters_done, void* stream);
+
+/*
+ * Eq. (1) for codebook `w` ([M][2], real type): D = log S_W + log S_X -
+ * 2 log S_XW, written to `d_out` (one double).
+ */
+itc_status itc_lattice_divergence(const itc_lattice_desc* d, const void* maps, const double* s_x,
+                                  int32_t M, const void* w, double* d_out, void* stream);
+
+/*
+ * Adjoint of itc_lattice_divergence (the derivative of q with respect to w_k,
+ * Section 3.1, with the sign and factor of the Gaussian derivative
+ * (x - w_k)/sigma^2; weights as in Section 5). Given dL/dD in `grad_d` (one
+ * double), writes
+ *   grad_w[k]      = dL/dD * ( -(2/S_XW) grad A_bil(w_k) + (2/(sigma^2 S_W)) E_k )
+ *   grad_weights(y) = dL/dD * ( 2 A(y)/S_X - (2/S_XW) K(y) ),
+ *   K(y) = sum_k sum_c beta_kc g(c - y)   (bilinear corner weights of w_k, window R)
+ * grad_w is [M][2] in the real type; grad_weights is height x width, row pitch
+ * `width`, in the real type, the derivative with respect to the weight
+ * h = weight_scale * stored. Either output may be NULL to skip it.
+ */
+itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void* maps,
+                                           const double* s_x, int32_t M, const void* w,
+                                           const double* grad_d, void* grad_w, void* grad_weights,
+                                           void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: n independent images of uneven size, each with its own M,
+ * sigma and iteration count, in flat device buffers. A plan is built once per
+ * batch layout; its calls launch one persistent kernel each (convolution
+ * over a cost-sorted tile queue; fit over a cost-sorted image queue) and
+ * contain no allocation, synchronisation or memset, so they can be captured
+ * into a HIP graph. Results are bitwise identical to the per-image calls.
+ * All images must use real_dtype ITC_F32.
+ * ------------------------------------------------------------------------ */
+typedef struct itc_plan itc_plan;
+
+typedef struct {
+  int32_t n;                    /* number of images, >= 1 */
+  const itc_lattice_desc* desc; /* host [n] */
+  const int64_t* weight_off;    /* host [n]: byte offset of image i in the weights buffer */
+  const int64_t* map_off;       /* host [n]: byte offset of image i's maps (256-aligned) */
+  const int32_t* M;             /* host [n]: codevectors of image i */
+  const int64_t* w_off;         /* host [n]: offset, in codevectors, of image i's codebook */
+  const int32_t* iters;         /* host [n]: sweeps for image i */
+} itc_batch;
+
+/* Validates every image and builds the plan (copies descriptors to the device). */
+itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out);
+
+/* Convolution maps of every image (one persistent launch). */
+itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void* maps, void* stream);
+
+/*
+ * Fit of every image (one persistent launch), then D at its final codebook.
+ * Writes w_out (same offsets as w_init; may alias), s_x[i] and d_out[i]
+ * (double [n], each may be NULL), iters_done[i] (int32 [n], may be NULL).
+ * theta applies to every image (< 0: run all sweeps).
+ */
+itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_init, double theta,
+                                   void* w_out, double* s_x, double* d_out, int32_t* iters_done,
+                                   void* stream);
+
+/* itc_lattice_precompute_batched followed by itc_lattice_fit_batched. */
+itc_status itc_lattice_run_batched(itc_plan* p, const void* weights, void* maps, const void* w_init,
+                                   double theta, void* w_out, double* s_x, double* d_out,
+                                   int32_t* iters_done, void* stream);
+
+/* Number of images in the plan, or -1 for NULL. */
+int32_t itc_lattice_plan_size(const itc_plan* p);
+
+/* Frees the plan's device descriptors (after the work using them is done). NULL is a no-op. */
+void itc_lattice_plan_destroy(itc_plan* p);
+
+/* Static text of a status code. */
+const char* itc_status_str(itc_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* itc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ITC_LATTICE_H */

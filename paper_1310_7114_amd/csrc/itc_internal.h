@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace itc {
+
+// ---------------------------------------------------------------------------
+// Convolution geometry: a workgroup owns a strip of CONV_TW columns and a
+// segment of rows; it streams down the segment in chunks of CONV_CH rows.
+// ---------------------------------------------------------------------------
+constexpr int CONV_TW = 64;    // strip width = one wave of lanes
+constexpr int CONV_CH = 16;    // rows per chunk
+constexpr int CONV_NT = 256;   // threads per workgroup (4 waves)
+constexpr int CONV_GROUP = 4;  // rows per S_X partial (one wave's rows in a chunk)
+constexpr int ITC_MAX_CODEVECTORS_DEV = 1024;
+
+// Supported truncation radii are rounded up to one of these classes; taps
+// beyond the true radius are zero, which leaves every sum unchanged.
+constexpr int kRadiusClassesF32[] = {2, 3, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24, 28, 32};
+constexpr int kRadiusClassesF64[] = {2, 3, 4, 6, 8, 12, 16};
+
+inline int radius_class(int R, bool f64) {
+  if (f64) {
+    for (int c : kRadiusClassesF64)
+      if (R <= c) return c;
+  } else {
+    for (int c : kRadiusClassesF32)
+      if (R <= c) return c;
+  }
+  return -1;
+}
+
+inline int64_t map_pitch_of(int W) { return ((int64_t)W + 63) / 64 * 64; }
+inline int n_strips(int W) { return (W + CONV_TW - 1) / CONV_TW; }
+inline int n_groups(int H) { return (H + CONV_GROUP - 1) / CONV_GROUP; }
+
+// One image as the kernels see it. Offsets are in bytes from the batch bases.
+struct ImageDesc {
+  int64_t weight_off;   // stored weights of this image
+  int64_t pitch;        // weight row pitch, elements
+  int64_t map_off;      // maps of this image (planes A, Mu, Mv, then partials)
+  int64_t map_pitch;    // elements per map row
+  int64_t part_off;     // byte offset of the S_X partials inside the maps
+  int64_t w_off;        // codebook offset, codevectors
+  double scale;         // h = scale * stored
+  double sigma;
+  int32_t H, W;
+  int32_t R;            // true radius (taps beyond it are zero)
+  int32_t rclass;       // compiled radius class >= R
+  int32_t wdtype;       // 0 u8, 1 f32, 2 f64
+  int32_t M;
+  int32_t iters;
+  int32_t nstrips;
+  int32_t ngroups;
+  int32_t pad_;
+};
+
+// A segment of one strip: output rows [s0, s0 + S) clipped to the image.
+struct ConvTile {
+  int32_t img;
+  int32_t strip;
+  int32_t s0;
+  int32_t S;
+};
+
+// Launchers (defined in the .hip files). All return hipError_t of the launch.
+// Single image (h_image by value, all strips and segments in one grid).
+hipError_t launch_conv_image(bool f64, const ImageDesc& h_image, const void* weights, void* maps,
+                             hipStream_t s);
+// Persistent launch over `ntiles` tiles of one radius class.
+hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, const ConvTile* d_tiles,
+                             int ntiles, const void* weights, void* maps, int grid, hipStream_t s);
+// Resident workgroups per compute unit of the persistent kernels (0 on error).
+int conv_tiles_blocks_per_cu(bool f64, int rclass);
+int fit_blocks_per_cu(bool f64, int m_max);
+// Segment rows used for a single image (multiple of CONV_CH).
+int conv_segment_rows(const ImageDesc& im);
+hipError_t launch_sx_finalize(bool f64, const ImageDesc& img, const void* maps, double* s_x,
+                              hipStream_t s);
+
+struct FitArgs {
+  const void* maps;      // batch base of maps
+  const void* w_init;    // batch base of codebooks
+  void* w_out;
+  double* s_x_out;       // [n] or null (batched: written from the partials)
+  const double* s_x_in;  // single image: precomputed S_X (may be null when not needed)
+  double* d_trace;       // single image: [iters+1] or null
+  double* d_out;         // [n] or null
+  int32_t* iters_done;   // [n] or null
+  double theta;
+  int32_t n;             // images
+  int32_t m_max;         // largest M (sizes the shared memory)
+  int32_t write_w;       // 0: do not write w_out (divergence only)
+};
+
+hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
+                      int grid, hipStream_t s, const ImageDesc* h_image);
+
+struct BackwardArgs {
+  const void* maps;
+  const void* w;
+  const double* s_x;
+  const double* grad_d;
+  void* grad_w;          // [M][2] or null
+  void* grad_weights;    // H x W or null
+  int32_t n;
+};
+
+hipError_t launch_backward(bool f64, const ImageDesc* d_images, const BackwardArgs& a, int grid_w,
+                           hipStream_t s, const ImageDesc* h_image);
+
+}  // namespace itc

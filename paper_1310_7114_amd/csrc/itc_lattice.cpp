@@ -1,0 +1,397 @@
+// C-ABI host layer of the lattice ITC library: argument validation, image
+// descriptors, batch plans and kernel launches. No allocation happens on the
+// per-call paths; plans allocate their device descriptor arrays once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "itc_internal.h"
+#include "itc_lattice.h"
+
+using itc::ConvTile;
+using itc::ImageDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+itc_status fail(itc_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+itc_status ok() {
+  g_last_error.clear();
+  return ITC_OK;
+}
+
+itc_status device_fail(hipError_t e, const char* where) {
+  return fail(ITC_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t real_size(int dt) { return dt == ITC_F64 ? 8 : 4; }
+
+int effective_radius(const itc_lattice_desc& d) {
+  if (d.radius > 0) return d.radius;
+  return (int)std::ceil(3.0 * d.sigma - 1e-12);
+}
+
+// Validates a descriptor; on success fills R and its compiled radius class.
+itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out) {
+  if (!d) return fail(ITC_E_NULL, "descriptor is NULL");
+  if (d->height < 1 || d->width < 1)
+    return fail(ITC_E_ARG, "height and width must be >= 1 (got %d x %d)", d->height, d->width);
+  if (d->height > (1 << 20) || d->width > (1 << 20))
+    return fail(ITC_E_ARG, "height and width must be <= 2^20 (got %d x %d)", d->height, d->width);
+  if (d->pitch < d->width) return fail(ITC_E_ARG, "pitch %lld < width %d", (long long)d->pitch, d->width);
+  if (d->weight_dtype < ITC_U8 || d->weight_dtype > ITC_F64)
+    return fail(ITC_E_ARG, "weight_dtype %d is not ITC_U8/ITC_F32/ITC_F64", d->weight_dtype);
+  if (d->real_dtype != ITC_F32 && d->real_dtype != ITC_F64)
+    return fail(ITC_E_ARG, "real_dtype %d is not ITC_F32/ITC_F64", d->real_dtype);
+  if (!std::isfinite(d->weight_scale)) return fail(ITC_E_ARG, "weight_scale is not finite");
+  if (!(d->sigma > 0.0) || !std::isfinite(d->sigma))
+    return fail(ITC_E_ARG, "sigma must be finite and > 0 (got %g)", d->sigma);
+  if (d->radius < 0) return fail(ITC_E_ARG, "radius must be >= 0 (got %d)", d->radius);
+  if (d->reserved != 0) return fail(ITC_E_ARG, "reserved must be 0");
+  if (d->sigma > 1e6) return fail(ITC_E_UNSUPPORTED, "sigma %g too large", d->sigma);
+  const int R = effective_radius(*d);
+  if (R < 1) return fail(ITC_E_ARG, "radius must be >= 1 (got %d)", R);
+  const bool f64 = d->real_dtype == ITC_F64;
+  const int rc = itc::radius_class(R, f64);
+  if (rc < 0)
+    return fail(ITC_E_UNSUPPORTED, "radius %d exceeds the compiled maximum %d for %s", R,
+                f64 ? ITC_MAX_RADIUS_F64 : ITC_MAX_RADIUS_F32, f64 ? "FP64" : "FP32");
+  if (R_out) *R_out = R;
+  if (rc_out) *rc_out = rc;
+  return ITC_OK;
+}
+
+size_t planes_bytes(const itc_lattice_desc& d) {
+  return (size_t)3 * d.height * itc::map_pitch_of(d.width) * real_size(d.real_dtype);
+}
+
+size_t maps_bytes_of(const itc_lattice_desc& d) {
+  const size_t part = (size_t)itc::n_strips(d.width) * itc::n_groups(d.height) * sizeof(double);
+  return (planes_bytes(d) + part + 255) / 256 * 256;
+}
+
+ImageDesc make_image(const itc_lattice_desc& d, int R, int rc) {
+  ImageDesc im;
+  std::memset(&im, 0, sizeof im);
+  im.pitch = d.pitch;
+  im.map_pitch = itc::map_pitch_of(d.width);
+  im.part_off = (int64_t)planes_bytes(d);
+  im.scale = d.weight_scale;
+  im.sigma = d.sigma;
+  im.H = d.height;
+  im.W = d.width;
+  im.R = R;
+  im.rclass = rc;
+  im.wdtype = d.weight_dtype;
+  im.nstrips = itc::n_strips(d.width);
+  im.ngroups = itc::n_groups(d.height);
+  return im;
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+    return 256;
+  return n;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+struct itc_plan {
+  int n = 0;
+  int m_max = 0;
+  std::vector<ImageDesc> images;
+  // tile list grouped by radius class: [begin, end) per class
+  std::vector<ConvTile> tiles;
+  std::vector<int> cls, cls_begin, cls_end, cls_grid;
+  std::vector<int32_t> order;  // fit order, most expensive first
+  int fit_grid = 1;
+  ImageDesc* d_images = nullptr;
+  ConvTile* d_tiles = nullptr;
+  int32_t* d_order = nullptr;
+};
+
+extern "C" {
+
+const char* itc_status_str(itc_status s) {
+  switch (s) {
+    case ITC_OK: return "ok";
+    case ITC_E_NULL: return "null pointer";
+    case ITC_E_ARG: return "invalid argument";
+    case ITC_E_UNSUPPORTED: return "unsupported size";
+    case ITC_E_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* itc_last_error(void) { return g_last_error.c_str(); }
+
+int32_t itc_lattice_radius(const itc_lattice_desc* d) {
+  int R = 0;
+  if (check_desc(d, &R, nullptr) != ITC_OK) return -1;
+  return R;
+}
+
+int64_t itc_lattice_map_pitch(const itc_lattice_desc* d) {
+  if (check_desc(d, nullptr, nullptr) != ITC_OK) return -1;
+  return itc::map_pitch_of(d->width);
+}
+
+size_t itc_lattice_maps_bytes(const itc_lattice_desc* d) {
+  if (check_desc(d, nullptr, nullptr) != ITC_OK) return 0;
+  return maps_bytes_of(*d);
+}
+
+itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights, void* maps, double* s_x,
+                                  void* stream) {
+  int R = 0, rc = 0;
+  itc_status st = check_desc(d, &R, &rc);
+  if (st != ITC_OK) return st;
+  if (!weights || !maps || !s_x) return fail(ITC_E_NULL, "weights, maps and s_x must be non-NULL");
+  if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  const bool f64 = d->real_dtype == ITC_F64;
+  const ImageDesc im = make_image(*d, R, rc);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = itc::launch_conv_image(f64, im, weights, maps, s);
+  if (e != hipSuccess) return device_fail(e, "convolution launch");
+  e = itc::launch_sx_finalize(f64, im, maps, s_x, s);
+  if (e != hipSuccess) return device_fail(e, "S_X launch");
+  return ok();
+}
+
+static itc_status fit_common(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
+                             const void* w_init, int32_t iters, double theta, void* w_out, double* d_trace,
+                             double* d_out, int32_t* iters_done, bool write_w, void* stream) {
+  int R = 0, rc = 0;
+  itc_status st = check_desc(d, &R, &rc);
+  if (st != ITC_OK) return st;
+  if (!maps || !w_init) return fail(ITC_E_NULL, "maps and the codebook must be non-NULL");
+  if (write_w && !w_out) return fail(ITC_E_NULL, "w_out must be non-NULL");
+  if ((d_trace || d_out) && !s_x) return fail(ITC_E_NULL, "s_x is required for the divergence");
+  if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
+  if (M > ITC_MAX_CODEVECTORS) return fail(ITC_E_UNSUPPORTED, "M %d exceeds %d", M, ITC_MAX_CODEVECTORS);
+  if (iters < 0) return fail(ITC_E_ARG, "iters must be >= 0 (got %d)", iters);
+  if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
+  if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  ImageDesc im = make_image(*d, R, rc);
+  im.M = M;
+  im.iters = iters;
+  itc::FitArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.maps = maps;
+  a.w_init = w_init;
+  a.w_out = w_out;
+  a.s_x_in = s_x;
+  a.d_trace = d_trace;
+  a.d_out = d_out;
+  a.iters_done = iters_done;
+  a.theta = theta;
+  a.n = 1;
+  a.m_max = M;
+  a.write_w = write_w ? 1 : 0;
+  hipError_t e = itc::launch_fit(d->real_dtype == ITC_F64, nullptr, nullptr, a, 1, (hipStream_t)stream, &im);
+  if (e != hipSuccess) return device_fail(e, "fit launch");
+  return ok();
+}
+
+itc_status itc_lattice_fit(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
+                           const void* w_init, int32_t iters, double theta, void* w_out, double* d_trace,
+                           int32_t* iters_done, void* stream) {
+  return fit_common(d, maps, s_x, M, w_init, iters, theta, w_out, d_trace, nullptr, iters_done, true, stream);
+}
+
+itc_status itc_lattice_divergence(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
+                                  const void* w, double* d_out, void* stream) {
+  if (!d_out) return fail(ITC_E_NULL, "d_out must be non-NULL");
+  if (!s_x) return fail(ITC_E_NULL, "s_x must be non-NULL");
+  return fit_common(d, maps, s_x, M, w, 0, -1.0, nullptr, nullptr, d_out, nullptr, false, stream);
+}
+
+itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void* maps, const double* s_x,
+                                           int32_t M, const void* w, const double* grad_d, void* grad_w,
+                                           void* grad_weights, void* stream) {
+  int R = 0, rc = 0;
+  itc_status st = check_desc(d, &R, &rc);
+  if (st != ITC_OK) return st;
+  (void)maps; (void)s_x; (void)M; (void)w; (void)grad_d; (void)grad_w; (void)grad_weights; (void)stream;
+  return fail(ITC_E_UNSUPPORTED, "divergence backward is not built yet");
+}
+
+// ---------------------------------------------------------------------------
+// batched
+// ---------------------------------------------------------------------------
+itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
+  if (!b || !out) return fail(ITC_E_NULL, "batch and out must be non-NULL");
+  *out = nullptr;
+  if (b->n < 1) return fail(ITC_E_ARG, "batch must hold >= 1 image (got %d)", b->n);
+  if (!b->desc || !b->weight_off || !b->map_off || !b->M || !b->w_off || !b->iters)
+    return fail(ITC_E_NULL, "batch arrays must be non-NULL");
+  itc_plan* p = new (std::nothrow) itc_plan;
+  if (!p) return fail(ITC_E_DEVICE, "out of host memory");
+  p->n = b->n;
+  p->images.resize(b->n);
+  std::vector<std::vector<ConvTile>> by_class(64);
+  std::vector<std::vector<int64_t>> cost_of(64);
+  std::vector<double> fit_cost(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    int R = 0, rc = 0;
+    itc_status st = check_desc(&b->desc[i], &R, &rc);
+    if (st != ITC_OK) {
+      std::string why = g_last_error;
+      delete p;
+      return fail(st, "image %d: %s", i, why.c_str());
+    }
+    const itc_lattice_desc& d = b->desc[i];
+    if (d.real_dtype != ITC_F32) {
+      delete p;
+      return fail(ITC_E_UNSUPPORTED, "image %d: the batched path is FP32 only", i);
+    }
+    if (b->M[i] < 1 || b->iters[i] < 0 || b->weight_off[i] < 0 || b->map_off[i] < 0 || b->w_off[i] < 0) {
+      delete p;
+      return fail(ITC_E_ARG, "image %d: M, iters and offsets must be non-negative (M >= 1)", i);
+    }
+    if (b->M[i] > ITC_MAX_CODEVECTORS) {
+      delete p;
+      return fail(ITC_E_UNSUPPORTED, "image %d: M %d exceeds %d", i, b->M[i], ITC_MAX_CODEVECTORS);
+    }
+    if (b->map_off[i] % 256 != 0) {
+      delete p;
+      return fail(ITC_E_ARG, "image %d: map_off must be a multiple of 256", i);
+    }
+    ImageDesc im = make_image(d, R, rc);
+    im.weight_off = b->weight_off[i];
+    im.map_off = b->map_off[i];
+    im.w_off = b->w_off[i];
+    im.M = b->M[i];
+    im.iters = b->iters[i];
+    p->images[i] = im;
+    p->m_max = std::max(p->m_max, im.M);
+    // tiles: segments of at most ~256 rows, multiples of the chunk height
+    int nseg = (im.H + 255) / 256;
+    int S = (im.H + nseg - 1) / nseg;
+    S = (S + itc::CONV_CH - 1) / itc::CONV_CH * itc::CONV_CH;
+    nseg = (im.H + S - 1) / S;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int rows = std::min(S, im.H - sg * S);
+      for (int st2 = 0; st2 < im.nstrips; ++st2) {
+        by_class[rc].push_back(ConvTile{i, st2, sg * S, S});
+        cost_of[rc].push_back((int64_t)(rows + 2 * rc) * (2 * rc + 1));
+      }
+    }
+    fit_cost[i] = (double)(im.iters + 1) * im.M * (im.M + 16.0);
+  }
+  for (int rc = 0; rc < 64; ++rc) {
+    if (by_class[rc].empty()) continue;
+    std::vector<int> idx(by_class[rc].size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cost_of[rc][a] > cost_of[rc][c]; });
+    p->cls.push_back(rc);
+    p->cls_begin.push_back((int)p->tiles.size());
+    for (int k : idx) p->tiles.push_back(by_class[rc][k]);
+    p->cls_end.push_back((int)p->tiles.size());
+  }
+  p->order.resize(b->n);
+  std::iota(p->order.begin(), p->order.end(), 0);
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int c) { return fit_cost[a] > fit_cost[c]; });
+
+  const int cus = device_cus();
+  for (size_t c = 0; c < p->cls.size(); ++c) {
+    int per = itc::conv_tiles_blocks_per_cu(false, p->cls[c]);
+    if (per < 1) per = 1;
+    p->cls_grid.push_back(std::min(p->cls_end[c] - p->cls_begin[c], per * cus));
+  }
+  int fper = itc::fit_blocks_per_cu(false, p->m_max);
+  if (fper < 1) fper = 1;
+  p->fit_grid = std::min(p->n, fper * cus);
+
+  hipError_t e = hipMalloc(&p->d_images, sizeof(ImageDesc) * p->n);
+  if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tiles.size()));
+  if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int32_t) * p->n);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_images, p->images.data(), sizeof(ImageDesc) * p->n, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->tiles.empty())
+    e = hipMemcpy(p->d_tiles, p->tiles.data(), sizeof(ConvTile) * p->tiles.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), sizeof(int32_t) * p->n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    itc_lattice_plan_destroy(p);
+    return device_fail(e, "plan upload");
+  }
+  *out = p;
+  return ok();
+}
+
+int32_t itc_lattice_plan_size(const itc_plan* p) { return p ? p->n : -1; }
+
+void itc_lattice_plan_destroy(itc_plan* p) {
+  if (!p) return;
+  if (p->d_images) (void)hipFree(p->d_images);
+  if (p->d_tiles) (void)hipFree(p->d_tiles);
+  if (p->d_order) (void)hipFree(p->d_order);
+  delete p;
+}
+
+itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void* maps, void* stream) {
+  if (!p || !weights || !maps) return fail(ITC_E_NULL, "plan, weights and maps must be non-NULL");
+  if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  for (size_t c = 0; c < p->cls.size(); ++c) {
+    hipError_t e = itc::launch_conv_tiles(false, p->cls[c], p->d_images, p->d_tiles + p->cls_begin[c],
+                                          p->cls_end[c] - p->cls_begin[c], weights, maps, p->cls_grid[c],
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "batched convolution launch");
+  }
+  return ok();
+}
+
+itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_init, double theta, void* w_out,
+                                   double* s_x, double* d_out, int32_t* iters_done, void* stream) {
+  if (!p || !maps || !w_init || !w_out) return fail(ITC_E_NULL, "plan, maps, w_init and w_out must be non-NULL");
+  if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
+  if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  itc::FitArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.maps = maps;
+  a.w_init = w_init;
+  a.w_out = w_out;
+  a.s_x_out = s_x;
+  a.d_out = d_out;
+  a.iters_done = iters_done;
+  a.theta = theta;
+  a.n = p->n;
+  a.m_max = p->m_max;
+  a.write_w = 1;
+  hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, (hipStream_t)stream, nullptr);
+  if (e != hipSuccess) return device_fail(e, "batched fit launch");
+  return ok();
+}
+
+itc_status itc_lattice_run_batched(itc_plan* p, const void* weights, void* maps, const void* w_init, double theta,
+                                   void* w_out, double* s_x, double* d_out, int32_t* iters_done, void* stream) {
+  itc_status st = itc_lattice_precompute_batched(p, weights, maps, stream);
+  if (st != ITC_OK) return st;
+  return itc_lattice_fit_batched(p, maps, w_init, theta, w_out, s_x, d_out, iters_done, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+"""Python binding of libitc_lattice.so: argument marshalling only.
+
+Every step of the clustering runs in the HIP kernels behind the C ABI
+(include/itc_lattice.h). PyTorch supplies device memory and the current
+stream. There is no CPU fallback: if the library or a GPU is missing, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libitc_lattice.so")
+
+ITC_U8, ITC_F32, ITC_F64 = 0, 1, 2
+ITC_MAX_CODEVECTORS = 1024
+STATUS = {0: "ITC_OK", 1: "ITC_E_NULL", 2: "ITC_E_ARG", 3: "ITC_E_UNSUPPORTED", 4: "ITC_E_DEVICE"}
+
+
+class ItcError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("pitch", ctypes.c_int64),
+                ("weight_dtype", ctypes.c_int32), ("real_dtype", ctypes.c_int32),
+                ("weight_scale", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("radius", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("desc", ctypes.POINTER(Desc)),
+                ("weight_off", ctypes.POINTER(ctypes.c_int64)), ("map_off", ctypes.POINTER(ctypes.c_int64)),
+                ("M", ctypes.POINTER(ctypes.c_int32)), ("w_off", ctypes.POINTER(ctypes.c_int64)),
+                ("iters", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(Desc)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "itc_lattice_radius": (ctypes.c_int32, [_DP]),
+    "itc_lattice_map_pitch": (ctypes.c_int64, [_DP]),
+    "itc_lattice_maps_bytes": (ctypes.c_size_t, [_DP]),
+    "itc_lattice_precompute": (ctypes.c_int, [_DP, _P, _P, _P, _P]),
+    "itc_lattice_fit": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                       _P, _P, _P, _P]),
+    "itc_lattice_divergence": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    "itc_lattice_divergence_backward": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "itc_lattice_plan_create": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_void_p)]),
+    "itc_lattice_precompute_batched": (ctypes.c_int, [_P, _P, _P, _P]),
+    "itc_lattice_fit_batched": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
+    "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
+    "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
+    "itc_lattice_plan_destroy": (None, [_P]),
+    "itc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "itc_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise ItcError(status, load().itc_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_WDT = {torch.uint8: ITC_U8, torch.float32: ITC_F32, torch.float64: ITC_F64}
+_RDT = {torch.float32: ITC_F32, torch.float64: ITC_F64}
+
+
+def radius_for(sigma: float) -> int:
+    """Default truncation radius ceil(3 sigma)."""
+    return int(math.ceil(3.0 * sigma - 1e-12))
+
+
+def make_desc(H: int, W: int, sigma: float, weight_dtype=torch.uint8, real_dtype=torch.float32,
+              scale: float = 1.0, radius: int = 0, pitch: Optional[int] = None) -> Desc:
+    return Desc(int(H), int(W), int(W if pitch is None else pitch), _WDT[weight_dtype], _RDT[real_dtype],
+                float(scale), float(sigma), int(radius), 0)
+
+
+def maps_bytes(desc: Desc) -> int:
+    n = load().itc_lattice_maps_bytes(ctypes.byref(desc))
+    if n == 0:
+        raise ItcError(2, load().itc_last_error().decode())
+    return int(n)
+
+
+def map_pitch(desc: Desc) -> int:
+    return int(load().itc_lattice_map_pitch(ctypes.byref(desc)))
+
+
+@dataclass
+class Maps:
+    """Device maps of one image: buffer (bytes), S_X, and the descriptor."""
+    desc: Desc
+    buf: torch.Tensor
+    s_x: torch.Tensor
+    real_dtype: torch.dtype
+
+    def planes(self):
+        """(A, M_u, M_v) as (H, W) views of the map buffer."""
+        H, W = self.desc.height, self.desc.width
+        mp = map_pitch(self.desc)
+        esz = torch.finfo(self.real_dtype).bits // 8
+        flat = self.buf[: 3 * H * mp * esz].view(self.real_dtype).view(3, H, mp)
+        return flat[0, :, :W], flat[1, :, :W], flat[2, :, :W]
+
+
+def alloc_maps(desc: Desc, device="cuda") -> torch.Tensor:
+    return torch.empty(maps_bytes(desc), dtype=torch.uint8, device=device)
+
+
+def precompute(weights: torch.Tensor, sigma: float, scale: float = 1.0, radius: int = 0,
+               real_dtype=torch.float32, out: Optional[Maps] = None) -> Maps:
+    """Convolution maps A, M_u, M_v and S_X of a (H, W) weight image on the GPU."""
+    if weights.dim() != 2:
+        raise ValueError("weights must be (H, W)")
+    if weights.stride(1) != 1:
+        weights = weights.contiguous()
+    H, W = weights.shape
+    desc = make_desc(H, W, sigma, weights.dtype, real_dtype, scale, radius, pitch=weights.stride(0))
+    if out is None:
+        out = Maps(desc, alloc_maps(desc, weights.device),
+                   torch.empty(1, dtype=torch.float64, device=weights.device), real_dtype)
+    _check(load().itc_lattice_precompute(ctypes.byref(desc), _ptr(weights), _ptr(out.buf), _ptr(out.s_x),
+                                         _stream()))
+    out.desc = desc
+    return out
+
+
+def fit(maps: Maps, w_init: torch.Tensor, iters: int, theta: float = -1.0, trace: bool = True,
+        w_out: Optional[torch.Tensor] = None):
+    """Runs `iters` sweeps; returns (W, D trace or None, iterations done tensor)."""
+    w_init = w_init.to(maps.real_dtype).contiguous()
+    M = int(w_init.shape[0])
+    if w_out is None:
+        w_out = torch.empty_like(w_init)
+    d_trace = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=w_init.device) if trace else None
+    done = torch.zeros(1, dtype=torch.int32, device=w_init.device)
+    _check(load().itc_lattice_fit(ctypes.byref(maps.desc), _ptr(maps.buf), _ptr(maps.s_x), M, _ptr(w_init),
+                                  int(iters), float(theta), _ptr(w_out), _ptr(d_trace), _ptr(done), _stream()))
+    return w_out, d_trace, done
+
+
+def divergence(maps: Maps, w: torch.Tensor) -> torch.Tensor:
+    """D of eq. (1) for codebook w, as a 1-element float64 device tensor."""
+    w = w.to(maps.real_dtype).contiguous()
+    d = torch.empty(1, dtype=torch.float64, device=w.device)
+    _check(load().itc_lattice_divergence(ctypes.byref(maps.desc), _ptr(maps.buf), _ptr(maps.s_x),
+                                         int(w.shape[0]), _ptr(w), _ptr(d), _stream()))
+    return d
+
+
+def divergence_backward(maps: Maps, w: torch.Tensor, grad_d: torch.Tensor, want_w=True, want_weights=True):
+    """(dL/dw [M,2], dL/dh [H,W]) for dL/dD = grad_d (1-element float64 device tensor)."""
+    w = w.to(maps.real_dtype).contiguous()
+    gw = torch.empty_like(w) if want_w else None
+    gI = torch.empty((maps.desc.height, maps.desc.width), dtype=maps.real_dtype, device=w.device) \
+        if want_weights else None
+    _check(load().itc_lattice_divergence_backward(ctypes.byref(maps.desc), _ptr(maps.buf), _ptr(maps.s_x),
+                                                  int(w.shape[0]), _ptr(w), _ptr(grad_d.to(torch.float64)),
+                                                  _ptr(gw), _ptr(gI), _stream()))
+    return gw, gI
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+class BatchPlan:
+    """A batch of images packed in flat device buffers, and its C plan.
+
+    images: sequence of (H, W) uint8/float tensors (host or device); ms: codevectors
+    per image; sigmas, scales, iters: per image. The packed weights, maps and
+    codebook buffers are allocated once here.
+    """
+
+    def __init__(self, images: Sequence[torch.Tensor], ms: Sequence[int], sigmas: Sequence[float],
+                 iters: Sequence[int], scales: Optional[Sequence[float]] = None,
+                 radii: Optional[Sequence[int]] = None, device="cuda"):
+        n = len(images)
+        if n == 0:
+            raise ValueError("empty batch")
+        scales = [1.0] * n if scales is None else list(scales)
+        radii = [0] * n if radii is None else list(radii)
+        dt = images[0].dtype
+        esz = torch.tensor([], dtype=dt).element_size()
+        self.n = n
+        self.descs = (Desc * n)()
+        wo, mo, wf, mlist, it = [], [], [], [], []
+        woff = moff = 0
+        foff = 0
+        for i, img in enumerate(images):
+            if img.dtype != dt:
+                raise ValueError("all images of a batch share one storage dtype")
+            H, W = img.shape
+            d = make_desc(H, W, sigmas[i], dt, torch.float32, scales[i], radii[i])
+            self.descs[i] = d
+            wo.append(woff)
+            woff += (H * W * esz + 255) // 256 * 256
+            mo.append(moff)
+            moff += maps_bytes(d)
+            wf.append(foff)
+            foff += int(ms[i])
+            mlist.append(int(ms[i]))
+            it.append(int(iters[i]))
+        self.weight_off = (ctypes.c_int64 * n)(*wo)
+        self.map_off = (ctypes.c_int64 * n)(*mo)
+        self.w_off_arr = (ctypes.c_int64 * n)(*wf)
+        self.M = (ctypes.c_int32 * n)(*mlist)
+        self.iters = (ctypes.c_int32 * n)(*it)
+        self.w_offsets = wf
+        self.ms = mlist
+        self.total_w = foff
+        self.weights = torch.zeros(woff // esz, dtype=dt, device=device)
+        for i, img in enumerate(images):
+            H, W = img.shape
+            self.weights[wo[i] // esz: wo[i] // esz + H * W].copy_(img.reshape(-1).to(device))
+        self.maps = torch.empty(max(moff, 256), dtype=torch.uint8, device=device)
+        self.map_off_list = mo
+        b = Batch(n, self.descs, self.weight_off, self.map_off, self.M, self.w_off_arr, self.iters)
+        h = ctypes.c_void_p()
+        _check(load().itc_lattice_plan_create(ctypes.byref(b), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.itc_lattice_plan_destroy(h)
+            self.handle = None
+
+    def pack_codebooks(self, ws: Sequence[torch.Tensor], device="cuda") -> torch.Tensor:
+        out = torch.empty((self.total_w, 2), dtype=torch.float32, device=device)
+        for i, w in enumerate(ws):
+            out[self.w_offsets[i]: self.w_offsets[i] + self.ms[i]].copy_(torch.as_tensor(w).to(device, torch.float32))
+        return out
+
+    def unpack(self, flat: torch.Tensor, i: int) -> torch.Tensor:
+        return flat[self.w_offsets[i]: self.w_offsets[i] + self.ms[i]]
+
+    def maps_of(self, i: int) -> Maps:
+        d = self.descs[i]
+        nb = maps_bytes(d)
+        buf = self.maps[self.map_off_list[i]: self.map_off_list[i] + nb]
+        return Maps(d, buf, torch.empty(1, dtype=torch.float64, device=self.maps.device), torch.float32)
+
+    def precompute(self):
+        _check(load().itc_lattice_precompute_batched(self.handle, _ptr(self.weights), _ptr(self.maps), _stream()))
+
+    def fit(self, w_init: torch.Tensor, w_out: torch.Tensor, s_x=None, d_out=None, iters_done=None,
+            theta: float = -1.0):
+        _check(load().itc_lattice_fit_batched(self.handle, _ptr(self.maps), _ptr(w_init), float(theta),
+                                              _ptr(w_out), _ptr(s_x), _ptr(d_out), _ptr(iters_done), _stream()))
+
+    def run(self, w_init: torch.Tensor, w_out: torch.Tensor, s_x=None, d_out=None, iters_done=None,
+            theta: float = -1.0):
+        _check(load().itc_lattice_run_batched(self.handle, _ptr(self.weights), _ptr(self.maps), _ptr(w_init),
+                                              float(theta), _ptr(w_out), _ptr(s_x), _ptr(d_out),
+                                              _ptr(iters_done), _stream()))

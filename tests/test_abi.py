@@ -1,0 +1,130 @@
+"""The C-ABI library loads, exports every function include/itc_lattice.h declares,
+and rejects bad arguments on the host before touching the device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "itc_lattice.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(itc_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def itc():
+    from paper_1310_7114_amd import itc as m
+    m.load()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("itc_lattice_precompute", "itc_lattice_fit", "itc_lattice_divergence",
+                 "itc_lattice_divergence_backward", "itc_lattice_plan_create", "itc_lattice_run_batched"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(itc):
+    lib = itc.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding knows every declared function too
+    assert set(declared_functions()) <= set(itc.SIGNATURES)
+
+
+def test_desc_layout_matches_header(itc):
+    # int32 H, W; int64 pitch; int32 x2; double x2; int32 x2  -> 48 bytes
+    assert ctypes.sizeof(itc.Desc) == 48
+
+
+def test_sizes_and_radius(itc):
+    lib = itc.load()
+    d = itc.make_desc(100, 130, 4.0)
+    assert lib.itc_lattice_radius(ctypes.byref(d)) == 12
+    assert lib.itc_lattice_map_pitch(ctypes.byref(d)) == 192
+    planes = 3 * 100 * 192 * 4
+    parts = 3 * 25 * 8
+    assert itc.maps_bytes(d) == (planes + parts + 255) // 256 * 256
+    d2 = itc.make_desc(10, 10, 2.0, radius=5)
+    assert lib.itc_lattice_radius(ctypes.byref(d2)) == 5
+    d3 = itc.make_desc(10, 10, 2.5)
+    assert lib.itc_lattice_radius(ctypes.byref(d3)) == 8
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("height", 0, 2), ("width", -3, 2), ("pitch", 5, 2), ("sigma", 0.0, 2), ("sigma", float("nan"), 2),
+    ("weight_dtype", 7, 2), ("real_dtype", 0, 2), ("radius", -1, 2), ("reserved", 1, 2),
+    ("radius", 33, 3), ("sigma", 11.0, 3),
+])
+def test_bad_descriptors_rejected(itc, field, value, status):
+    lib = itc.load()
+    d = itc.make_desc(16, 16, 2.0)
+    setattr(d, field, value)
+    st = lib.itc_lattice_precompute(ctypes.byref(d), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                    ctypes.c_void_p(256), None)
+    assert st == status, lib.itc_last_error()
+    assert lib.itc_last_error()  # a reason is given
+    assert lib.itc_lattice_maps_bytes(ctypes.byref(d)) == 0
+
+
+def test_f64_radius_limit(itc):
+    lib = itc.load()
+    d = itc.make_desc(16, 16, 2.0, real_dtype=__import__("torch").float64, radius=17)
+    assert lib.itc_lattice_precompute(ctypes.byref(d), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                      ctypes.c_void_p(256), None) == 3
+
+
+def test_null_and_range_arguments(itc):
+    lib = itc.load()
+    P = ctypes.c_void_p(256)
+    assert lib.itc_lattice_precompute(None, P, P, P, None) == 1
+    d = itc.make_desc(16, 16, 2.0)
+    assert lib.itc_lattice_precompute(ctypes.byref(d), None, P, P, None) == 1
+    assert lib.itc_lattice_precompute(ctypes.byref(d), P, ctypes.c_void_p(260), P, None) == 2  # misaligned maps
+    fit = lib.itc_lattice_fit
+    assert fit(ctypes.byref(d), P, P, 0, P, 10, -1.0, P, None, None, None) == 2          # M = 0
+    assert fit(ctypes.byref(d), P, P, 1025, P, 10, -1.0, P, None, None, None) == 3       # M too large
+    assert fit(ctypes.byref(d), P, P, 4, P, -1, -1.0, P, None, None, None) == 2          # iters < 0
+    assert fit(ctypes.byref(d), P, P, 4, P, 3, float("nan"), P, None, None, None) == 2   # theta NaN
+    assert fit(ctypes.byref(d), P, None, 4, P, 3, -1.0, P, P, None, None) == 1           # trace needs s_x
+    assert fit(ctypes.byref(d), None, P, 4, P, 3, -1.0, P, None, None, None) == 1
+    assert lib.itc_lattice_divergence(ctypes.byref(d), P, P, 4, P, None, None) == 1
+    assert lib.itc_lattice_fit_batched(None, P, P, -1.0, P, None, None, None, None) == 1
+    assert lib.itc_lattice_plan_size(None) == -1
+    lib.itc_lattice_plan_destroy(None)
+
+
+def test_plan_rejects_bad_batches(itc):
+    lib = itc.load()
+    h = ctypes.c_void_p()
+    assert lib.itc_lattice_plan_create(None, ctypes.byref(h)) == 1
+    n = 2
+    descs = (itc.Desc * n)(itc.make_desc(8, 8, 1.0), itc.make_desc(8, 8, 1.0))
+    z64 = (ctypes.c_int64 * n)(0, 0)
+    ms = (ctypes.c_int32 * n)(4, 0)                       # M = 0 for image 1
+    it = (ctypes.c_int32 * n)(3, 3)
+    b = itc.Batch(n, descs, z64, z64, ms, z64, it)
+    assert lib.itc_lattice_plan_create(ctypes.byref(b), ctypes.byref(h)) == 2
+    assert b"image 1" in lib.itc_last_error()
+    ms2 = (ctypes.c_int32 * n)(4, 4)
+    moff = (ctypes.c_int64 * n)(0, 100)                   # misaligned map offset
+    b2 = itc.Batch(n, descs, z64, moff, ms2, z64, it)
+    assert lib.itc_lattice_plan_create(ctypes.byref(b2), ctypes.byref(h)) == 2
+    descs[1].real_dtype = 2
+    b3 = itc.Batch(n, descs, z64, z64, ms2, z64, it)
+    assert lib.itc_lattice_plan_create(ctypes.byref(b3), ctypes.byref(h)) == 3
+    assert lib.itc_lattice_plan_create(ctypes.byref(itc.Batch(0, descs, z64, z64, ms2, z64, it)),
+                                       ctypes.byref(h)) == 2
+
+
+def test_status_strings(itc):
+    lib = itc.load()
+    assert lib.itc_status_str(0) == b"ok"
+    assert lib.itc_status_str(3) == b"unsupported size"

@@ -1,0 +1,96 @@
+"""Batched persistent form vs the per-image calls and the oracle (config 3)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1310_7114_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def make_plan(itc, cases):
+    imgs = [torch.from_numpy(c.img) for c in cases]
+    plan = itc.BatchPlan(imgs, [c.M for c in cases], [c.sigma for c in cases], [c.iters for c in cases],
+                         scales=[c.scale for c in cases])
+    w0 = plan.pack_codebooks([c.w0 for c in cases])
+    return plan, w0
+
+
+def run_plan(plan, w0, theta=-1.0):
+    n = plan.n
+    w = torch.empty_like(w0)
+    sx = torch.empty(n, dtype=torch.float64, device="cuda")
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    done = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan.run(w0, w, sx, d, done, theta)
+    torch.cuda.synchronize()
+    return w, sx, d, done
+
+
+def test_batched_equals_per_image_bitwise(gpu_lib):
+    """A 64-image slice of the silhouette batch: batched results are bitwise the per-image ones."""
+    cases = S.config3_cases(indices=range(64))
+    plan, w0 = make_plan(gpu_lib, cases)
+    w, sx, d, done = run_plan(plan, w0)
+    for i, c in enumerate(cases):
+        img = torch.from_numpy(c.img).cuda()
+        m = gpu_lib.precompute(img, c.sigma, scale=c.scale)
+        wi, tr, di = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda(), c.iters)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.unpack(w, i), wi), i
+        assert float(sx[i]) == float(m.s_x[0]), i
+        assert float(d[i]) == float(tr[-1]), i
+        assert int(done[i]) == c.iters
+        # maps inside the packed buffer equal the per-image maps
+        pb = plan.maps_of(i).planes()
+        for x, y in zip(pb, m.planes()):
+            assert torch.equal(x, y), i
+
+
+def test_full_batch_sampled_against_oracle(gpu_lib):
+    """All 1,400 silhouettes in one plan (the benchmark's launch configuration);
+    sampled images are checked against the oracle one by one."""
+    cases = S.config3_cases()
+    plan, w0 = make_plan(gpu_lib, cases)
+    w, sx, d, done = run_plan(plan, w0)
+    assert torch.all(done == 100)
+    assert torch.all(torch.isfinite(d))
+    rng = np.random.default_rng(0)
+    sample = sorted(set([0, len(cases) - 1] + list(rng.choice(len(cases), 5, replace=False))))
+    for i in sample:
+        c = cases[i]
+        W_ref, tr_ref, _, maps_ref = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters)
+        got = plan.unpack(w, i).cpu().double().numpy()
+        assert np.linalg.norm(got - W_ref, axis=1).max() <= 1e-3, (i, c.sigma, c.M)
+        assert abs(float(d[i]) - tr_ref[-1]) <= 1e-5 * max(1.0, abs(tr_ref[-1])), i
+        assert float(sx[i]) == pytest.approx(float(np.sum(c.weights * maps_ref[0])), rel=1e-6)
+
+
+def test_batched_theta_and_graph_replay(gpu_lib):
+    """The plan's launches capture into a HIP graph; every replay matches eager."""
+    cases = S.config3_cases(indices=range(100, 116))
+    plan, w0 = make_plan(gpu_lib, cases)
+    w_e, sx_e, d_e, done_e = run_plan(plan, w0, theta=1e-3)
+    assert torch.all(done_e <= 100)
+    n = plan.n
+    w = torch.empty_like(w0)
+    sx = torch.empty(n, dtype=torch.float64, device="cuda")
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    done = torch.empty(n, dtype=torch.int32, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run(w0, w, sx, d, done, 1e-3)        # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run(w0, w, sx, d, done, 1e-3)
+    for _ in range(3):
+        w.zero_(); d.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(w, w_e) and torch.equal(d, d_e) and torch.equal(done, done_e)
+        assert torch.equal(sx, sx_e)
