@@ -40,7 +40,8 @@
  *    gives the reason. No C++ exception crosses this boundary.
  *  - Checks that fail return ITC_E_NULL (null pointer), ITC_E_ARG (a size,
  *    width or count out of range), ITC_E_UNSUPPORTED (valid but beyond what
- *    the kernels are built for: R > 32 for FP32, R > 16 for FP64, M > 1024),
+ *    the kernels are built for: R > 32 for FP32, R > 16 for FP64, M > 1024,
+ *    an image or its maps of 2 GiB or more),
  *    ITC_E_DEVICE (a HIP launch or runtime error).
  */
 #ifndef ITC_LATTICE_H
@@ -98,10 +99,10 @@ int64_t itc_lattice_map_pitch(const itc_lattice_desc* d);
 
 /*
  * Bytes of the maps buffer for `d`, 0 if `d` is invalid. Layout (all in the
- * real type unless stated): plane A, then plane M_u, then plane M_v, each
- * height x map_pitch row-major; then a trailer of ceil(width/64) x
- * ceil(height/4) FP64 partial sums of S_X (library-internal). The size is a
- * multiple of 256 bytes; the buffer must be 256-byte aligned.
+ * real type): plane A, then plane M_u, then plane M_v, each height x
+ * map_pitch row-major; then a trailer of ceil(width/64) x ceil(height/8) x 64
+ * partial sums of S_X (library-internal). The size is a multiple of 256
+ * bytes; the buffer must be 256-byte aligned.
  */
 size_t itc_lattice_maps_bytes(const itc_lattice_desc* d);
 
@@ -109,7 +110,7 @@ size_t itc_lattice_maps_bytes(const itc_lattice_desc* d);
  * Section 3.1 / Algorithm 1 "compute P once": the convolution maps of the
  * weight image and S_X. `weights` points at the stored image (layout in `d`),
  * `maps` at itc_lattice_maps_bytes(d) bytes (written), `s_x` at one double
- * (written). Map columns beyond `width` inside the pitch are left untouched.
+ * (written). Map columns beyond `width` inside the pitch get unspecified values.
  */
 itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights, void* maps,
                                   double* s_x, void* stream);

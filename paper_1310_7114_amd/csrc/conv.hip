@@ -2,62 +2,162 @@
 // the Parzen sum of delta impulses is the image convolved with a Gaussian; for
 // small widths the 2-D mask factorises into 1-D masks). One pass produces
 //   A   = (I *_v g) *_u g,   M_u = (I *_v g) *_u tg,   M_v = (I *_v tg) *_u g
-// with g[t] = exp(-t^2/(2 sigma^2)), tg[t] = t g[t], |t| <= R, and per 4-row
-// group FP64 partial sums of S_X = sum I A.
+// with g[t] = exp(-t^2/(2 sigma^2)), tg[t] = t g[t], |t| <= R, and partial
+// sums of S_X = sum I A (one per lane and 8-row group; summed in FP64 later).
 //
-// Work decomposition (gfx950): a 256-thread workgroup owns a strip of 64
-// columns and a segment of rows and streams down it in chunks of 16 rows.
-// Per chunk:
-//   1. the chunk's input rows (with an R-column halo on both sides) are staged
-//      in LDS as the real type (prefetched into registers one chunk ahead);
-//   2. row pass (along v): each thread makes 4 adjacent columns of R0 = I*g and
-//      R1 = I*tg for one row and writes them into an LDS ring of the last
-//      2R+16 rows. Every row is written twice (slot q and q + RING) so that any
-//      window of 2R+4 consecutive rows is contiguous: the column pass then
-//      addresses all its reads with compile-time offsets from one base;
-//   3. column pass (along u, lags the row pass by R rows): each thread makes 4
-//      consecutive rows of one column of A, M_u, M_v, stores them coalesced
-//      (lanes = columns) and adds h*A to the wave's S_X partial.
-// Taps are computed once per workgroup in FP64 (one per lane) and held in
-// scalar registers; the tap loops are fully unrolled for the radius class.
+// Work decomposition (gfx950): a workgroup of two waves owns a strip of 64
+// columns (lane = column) and a segment of rows, and streams down it in
+// chunks of 16 rows. Per chunk:
+//   1. staging: the chunk's 16 input rows, with an R-column halo on each side,
+//      are converted to the real type and written to LDS. Their global loads
+//      were issued one chunk earlier into registers, behind the arithmetic;
+//   2. row pass (along v): each lane makes 4 adjacent columns of R0 = I*g and
+//      R1 = I*tg for 2 rows and writes them into an LDS ring holding the last
+//      2R + 16 rows (a whole number of 16-row blocks);
+//   3. column pass (along u, R rows behind the row pass): wave w makes rows
+//      8w..8w+7 of the chunk for its lane's column: A, M_u, M_v (24
+//      accumulators). A 16-row block of the ring never wraps, and the block
+//      and offset of every read are compile-time for a given w, so each read
+//      is one base register plus an immediate offset. Outputs are stored
+//      coalesced (lanes = columns); h*A is summed per lane into an S_X partial.
+// Two waves per workgroup keep two waves on every SIMD at the LDS budget of
+// one ring, so one wave's LDS, scalar and memory instructions issue beside
+// the other's FMAs. Taps are computed once per segment in FP64 (one lane per
+// tap) and held in scalar registers; tap loops are unrolled for the class.
 #include "itc_device.h"
 
 namespace itc {
 
 template <typename T, int R>
 struct ConvGeom {
-  static constexpr int J0 = (2 * R + CONV_CH - 1) / CONV_CH;  // chunks before the first column pass
-  static constexpr int RING = (J0 + 1) * CONV_CH;             // ring rows, >= 2R + CH
-  static constexpr int NXL = 2 * R + 4;                       // row-pass inputs per thread
-  static constexpr int XP = 60 + 4 * ((NXL + 3) / 4);         // staging row pitch (elements)
-  static constexpr int XW = CONV_TW + 2 * R;                  // staged columns per row
-  static constexpr int NSTAGE = (CONV_CH * XW + CONV_NT - 1) / CONV_NT;  // staged elements per thread
-  static constexpr size_t RING_ELEMS = (size_t)2 * RING * CONV_TW;        // one plane, doubled
-  static constexpr size_t SMEM = (2 * RING_ELEMS + (size_t)CONV_CH * XP) * sizeof(T);
+  static constexpr int CH = CONV_CH;
+  static constexpr int J0 = (2 * R + CH - 1) / CH;  // chunks before the first column pass
+  static constexpr int NB = J0 + 1;                 // ring blocks of CH rows
+  static constexpr int RING = NB * CH;              // >= 2R + CH
+  static constexpr int NWIN = 2 * R + CONV_KB;      // rows a lane reads per column pass
+  static constexpr int NXL = 2 * R + 4;             // row-pass inputs per lane and row
+  static constexpr int XP = 2 * CONV_TW;            // staging row pitch: two staged columns per lane
+  static constexpr int XW = CONV_TW + 2 * R;        // staged columns per row (<= 128)
+  static constexpr size_t RING_ELEMS = (size_t)RING * CONV_TW;
+  static constexpr size_t SMEM = (2 * RING_ELEMS + (size_t)CH * XP) * sizeof(T);
+  static_assert(XW <= 2 * CONV_TW, "two staged columns per lane");
 };
+
+// Raw stored weight at element offset `i`, kept unconverted until staging so
+// that the global load's latency hides behind a whole chunk of arithmetic.
+// FP32 kernels keep 32 bits (u8 value or f32 bits; FP64 weights are narrowed
+// to f32 at load), FP64 kernels keep 64 bits.
+template <typename T>
+struct RawOf {
+  using type = uint32_t;
+};
+template <>
+struct RawOf<double> {
+  using type = uint64_t;
+};
+
+// Load of a stored weight of type WT kept as raw bits (FP64 weights are
+// narrowed to f32 in FP32 kernels), and its conversion to the real type.
+template <typename T, typename WT>
+__device__ __forceinline__ typename RawOf<T>::type load_raw(rsrc_t r, uint32_t voff, uint32_t soff) {
+  using U = typename RawOf<T>::type;
+  const WT v = buf_load<WT>(r, voff, soff);
+  if constexpr (sizeof(WT) == 1)
+    return (U)v;
+  else if constexpr (sizeof(WT) == 4)
+    return (U)__builtin_bit_cast(uint32_t, v);
+  else if constexpr (sizeof(U) == 8)
+    return __builtin_bit_cast(uint64_t, v);
+  else
+    return __builtin_bit_cast(uint32_t, (float)v);
+}
+template <typename T, typename WT>
+__device__ __forceinline__ T raw_value(typename RawOf<T>::type r) {
+  if constexpr (sizeof(WT) == 1)
+    return (T)(uint32_t)r;
+  else if constexpr (sizeof(WT) == 4 || sizeof(r) == 4)
+    return (T)__builtin_bit_cast(float, (uint32_t)r);
+  else
+    return (T)__builtin_bit_cast(double, (uint64_t)r);
+}
+
+// Calls f(WT{}) with WT the stored weight type: one uniform branch per call.
+template <typename F>
+__device__ __forceinline__ void with_weight_type(int wdtype, F&& f) {
+  if (wdtype == 0)
+    f(uint8_t{});
+  else if (wdtype == 1)
+    f(float{});
+  else
+    f(double{});
+}
+
+// Column pass of one wave: rows 8w..8w+7 of the chunk whose window starts at
+// ring block `jb` (chunk index minus J0).
+template <typename T, int R, int WV>
+__device__ __forceinline__ void column_pass(const T* __restrict__ ring0, const T* __restrict__ ring1, int jb,
+                                            int lane, const T (&g)[R + 1], const T (&tg)[R + 1],
+                                            T (&a)[CONV_KB], T (&mu)[CONV_KB], T (&mv)[CONV_KB]) {
+  using G = ConvGeom<T, R>;
+  constexpr int KB = CONV_KB;
+  constexpr int NBLK = (WV * KB + G::NWIN + CONV_CH - 1) / CONV_CH;  // blocks touched
+#pragma unroll
+  for (int k = 0; k < KB; ++k) a[k] = mu[k] = mv[k] = (T)0;
+#pragma unroll
+  for (int b = 0; b < NBLK; ++b) {
+    const int slot = ((jb + b) % G::NB) * CONV_CH;
+    const T* p0 = ring0 + slot * CONV_TW + lane;
+    const T* p1 = ring1 + slot * CONV_TW + lane;
+#pragma unroll
+    for (int ii = 0; ii < CONV_CH; ++ii) {
+      const int i = b * CONV_CH + ii - WV * KB;  // window row: absolute row o - R + i for output o = first + k
+      if (i >= 0 && i < G::NWIN) {
+        const T y = p0[ii * CONV_TW];
+        const T z = p1[ii * CONV_TW];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          const int s = k + R - i;
+          if (s >= -R && s <= R) {
+            const T gs = g[s < 0 ? -s : s];
+            a[k] = fma_t(gs, y, a[k]);
+            mv[k] = fma_t(gs, z, mv[k]);
+            if (s > 0) mu[k] = fma_t(tg[s], y, mu[k]);
+            if (s < 0) mu[k] = fma_t(-tg[-s], y, mu[k]);
+          }
+        }
+      }
+    }
+  }
+}
 
 template <typename T, int R>
 __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int s0, int S,
                                              const char* __restrict__ wbase, char* __restrict__ mbase,
                                              char* __restrict__ smem) {
   using G = ConvGeom<T, R>;
+  constexpr int CH = CONV_CH, KB = CONV_KB;
+  using Raw = typename RawOf<T>::type;
   T* ring0 = reinterpret_cast<T*>(smem);
   T* ring1 = ring0 + G::RING_ELEMS;
   T* xin = ring1 + G::RING_ELEMS;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int H = im.H, W = im.W;
   const int v0 = strip * CONV_TW;
   const int seg_end = min(s0 + S, H);
-  const int n_out = (seg_end - s0 + CONV_CH - 1) / CONV_CH;
+  const int n_out = (seg_end - s0 + CH - 1) / CH;
   const int nchunks = G::J0 + n_out;
-  const int origin = s0 - R;                 // absolute row of ring row 0
+  const int origin = s0 - R;                 // absolute row of relative row 0
   const int need_end = min(H, seg_end + R);  // row-pass rows at or past this are never read
 
-  const char* wimg = wbase + im.weight_off;
   const int wdtype = im.wdtype;
-  const int64_t pitch = im.pitch;
-  const double scale = im.scale;
+  const int esz = wdtype == 0 ? 1 : (wdtype == 1 ? 4 : 8);
+  const uint32_t rowbytes = (uint32_t)(im.pitch * esz);
+  const rsrc_t wres = make_rsrc(wbase + im.weight_off, (uint32_t)H * rowbytes);
+  const rsrc_t mres = make_rsrc(mbase + im.map_off, (uint32_t)(im.part_off + (int64_t)im.nstrips * im.ngroups *
+                                                                             CONV_TW * sizeof(T)));
+  const T scale = (T)im.scale;
 
   // ---- taps: g[t], tg[t] for t = 0..R (zero beyond the true radius) ----
   T g[R + 1], tg[R + 1];
@@ -72,37 +172,66 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
     }
   }
 
-  // ---- staging of chunk j's input rows into registers ----
-  T pre[G::NSTAGE];
+  // ---- staging: wave w fetches rows 8w..8w+7 of a chunk, columns c = lane and lane + 64 ----
+  const int col0 = v0 - R + lane, col1 = col0 + CONV_TW;
+  const bool ok0 = col0 >= 0 && col0 < W;
+  const bool ok1 = lane + CONV_TW < G::XW && col1 >= 0 && col1 < W;
+  const uint32_t off0 = ok0 ? (uint32_t)col0 : 0u, off1 = ok1 ? (uint32_t)col1 : 0u;
+  Raw raw0[KB], raw1[KB];
   auto fetch = [&](int j) {
+    const int y0 = origin + j * CH + wave * KB;
+    with_weight_type(wdtype, [&](auto wt) {
+      using WT = decltype(wt);
+      const uint32_t b0 = off0 * (uint32_t)sizeof(WT), b1 = off1 * (uint32_t)sizeof(WT);
+      if (y0 >= 0 && y0 + KB <= H) {  // all rows inside: loads at clamped columns, then select
+        uint32_t so = (uint32_t)y0 * rowbytes;
 #pragma unroll
-    for (int e = 0; e < G::NSTAGE; ++e) {
-      const int idx = tid + e * CONV_NT;
-      T v = (T)0;
-      if (idx < CONV_CH * G::XW) {
-        const int r = idx / G::XW, c = idx - r * G::XW;
-        v = (T)load_weight(wimg, wdtype, pitch, H, W, origin + j * CONV_CH + r, v0 - R + c, scale);
+        for (int r = 0; r < KB; ++r) {
+          const Raw a0 = load_raw<T, WT>(wres, b0, so);
+          const Raw a1 = load_raw<T, WT>(wres, b1, so);
+          raw0[r] = ok0 ? a0 : (Raw)0;
+          raw1[r] = ok1 ? a1 : (Raw)0;
+          so += rowbytes;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < KB; ++r) {
+          const int y = y0 + r;
+          const bool in = y >= 0 && y < H;
+          const uint32_t so = in ? (uint32_t)y * rowbytes : 0u;
+          Raw a0 = (Raw)0, a1 = (Raw)0;
+          if (in) {
+            a0 = load_raw<T, WT>(wres, b0, so);
+            a1 = load_raw<T, WT>(wres, b1, so);
+          }
+          raw0[r] = ok0 ? a0 : (Raw)0;
+          raw1[r] = ok1 ? a1 : (Raw)0;
+        }
       }
-      pre[e] = v;
-    }
+    });
   };
+  // every lane writes both of its staged columns (columns >= XW are never read)
   auto stage = [&]() {
+    T* x = xin + wave * KB * G::XP + lane;
+    with_weight_type(wdtype, [&](auto wt) {
+      using WT = decltype(wt);
 #pragma unroll
-    for (int e = 0; e < G::NSTAGE; ++e) {
-      const int idx = tid + e * CONV_NT;
-      if (idx < CONV_CH * G::XW) {
-        const int r = idx / G::XW, c = idx - r * G::XW;
-        xin[r * G::XP + c] = pre[e];
+      for (int r = 0; r < KB; ++r) {
+        x[r * G::XP] = raw_value<T, WT>(raw0[r]) * scale;
+        x[r * G::XP + CONV_TW] = raw_value<T, WT>(raw1[r]) * scale;
       }
-    }
+    });
   };
 
-  T* Aout = reinterpret_cast<T*>(mbase + im.map_off);
-  T* Muout = Aout + (size_t)H * im.map_pitch;
-  T* Mvout = Muout + (size_t)H * im.map_pitch;
-  double* part = reinterpret_cast<double*>(mbase + im.map_off + im.part_off);
+  const uint32_t mpb = (uint32_t)(im.map_pitch * sizeof(T));     // bytes per map row
+  const uint32_t planeb = (uint32_t)H * mpb;                       // bytes per plane
+  const int col = v0 + lane;
+  const bool col_ok = col < W;
+  const uint32_t hoff = col_ok ? (uint32_t)col : 0u;
+  const uint32_t mvoff = (uint32_t)col * (uint32_t)sizeof(T);     // inside the padded pitch
+  const uint32_t part_base = (uint32_t)im.part_off + (uint32_t)((int64_t)strip * im.ngroups * CONV_TW * sizeof(T));
 
-  const int rr = tid >> 4, cg = tid & 15;  // row pass: chunk row, column group of 4
+  const int rq = lane >> 4, cg = lane & 15;  // row pass: row in a set of 4, column group of 4
 
   fetch(0);
   for (int j = 0; j < nchunks; ++j) {
@@ -112,83 +241,88 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
 
     // ---------------- row pass: ring rows of chunk j ----------------
     {
-      const int first = origin + j * CONV_CH;
-      const int q = (j * CONV_CH) % G::RING + rr;
-      T r0[4], r1[4];
+      const int first = origin + j * CH;
+      const int slot0 = (j % G::NB) * CH;
+      const bool live = first + CH > 0 && first < need_end;
+#pragma unroll 1
+      for (int m = 0; m < KB / 4; ++m) {
+        const int r = wave * KB + rq + 4 * m;
+        T r0[4], r1[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) r0[k] = r1[k] = (T)0;
-      if (first + CONV_CH > 0 && first < need_end) {
-        const T* xr = xin + rr * G::XP + 4 * cg;
-        T x[G::NXL];
+        for (int c = 0; c < 4; ++c) r0[c] = r1[c] = (T)0;
+        if (live) {
+          const T* xr = xin + r * G::XP + 4 * cg;
+          T x[G::NXL];
 #pragma unroll
-        for (int i = 0; i < G::NXL; ++i) x[i] = xr[i];
+          for (int i = 0; i < G::NXL; ++i) x[i] = xr[i];
 #pragma unroll
-        for (int i = 0; i < G::NXL; ++i) {
+          for (int i = 0; i < G::NXL; ++i) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int s = k + R - i;  // tap index t = x_out - x_in
-            if (s >= -R && s <= R) {
-              r0[k] = fma_t(g[s < 0 ? -s : s], x[i], r0[k]);
-              if (s > 0) r1[k] = fma_t(tg[s], x[i], r1[k]);
-              if (s < 0) r1[k] = fma_t(-tg[-s], x[i], r1[k]);
+            for (int c = 0; c < 4; ++c) {
+              const int s = c + R - i;  // tap index t = x_out - x_in
+              if (s >= -R && s <= R) {
+                r0[c] = fma_t(g[s < 0 ? -s : s], x[i], r0[c]);
+                if (s > 0) r1[c] = fma_t(tg[s], x[i], r1[c]);
+                if (s < 0) r1[c] = fma_t(-tg[-s], x[i], r1[c]);
+              }
             }
           }
         }
-      }
-      T* d0 = ring0 + q * CONV_TW + 4 * cg;
-      T* d1 = ring1 + q * CONV_TW + 4 * cg;
+        T* d0 = ring0 + (slot0 + r) * CONV_TW + 4 * cg;
+        T* d1 = ring1 + (slot0 + r) * CONV_TW + 4 * cg;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        d0[k] = r0[k];
-        d0[k + G::RING * CONV_TW] = r0[k];
-        d1[k] = r1[k];
-        d1[k + G::RING * CONV_TW] = r1[k];
+        for (int c = 0; c < 4; ++c) {
+          d0[c] = r0[c];
+          d1[c] = r1[c];
+        }
       }
     }
     __syncthreads();
 
-    // ---------------- column pass: output rows of chunk j - J0 ----------------
+    // ---------------- column pass: rows 8w..8w+7 of output chunk j - J0 ----------------
     if (j >= G::J0) {
-      const int ob = (j - G::J0) * CONV_CH;
-      const int ofirst = s0 + ob + 4 * wave;
-      if (ofirst < seg_end) {
-        const int sb = ob % G::RING + 4 * wave;
-        const T* p0 = ring0 + sb * CONV_TW + lane;
-        const T* p1 = ring1 + sb * CONV_TW + lane;
-        T a[4], mu[4], mv[4];
+      const int o0 = s0 + (j - G::J0) * CH + wave * KB;
+      if (o0 < seg_end) {
+        Raw hraw[KB];  // weights of the output rows for S_X, loaded before the arithmetic
+        with_weight_type(wdtype, [&](auto wt) {
+          using WT = decltype(wt);
+          const uint32_t hb = hoff * (uint32_t)sizeof(WT);
+          uint32_t so = (uint32_t)o0 * rowbytes;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = mu[k] = mv[k] = (T)0;
-#pragma unroll
-        for (int i = 0; i < G::NXL; ++i) {
-          const T y = p0[i * CONV_TW];
-          const T z = p1[i * CONV_TW];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int s = k + R - i;
-            if (s >= -R && s <= R) {
-              const T gs = g[s < 0 ? -s : s];
-              a[k] = fma_t(gs, y, a[k]);
-              mv[k] = fma_t(gs, z, mv[k]);
-              if (s > 0) mu[k] = fma_t(tg[s], y, mu[k]);
-              if (s < 0) mu[k] = fma_t(-tg[-s], y, mu[k]);
-            }
+          for (int k = 0; k < KB; ++k) {
+            Raw v = (Raw)0;
+            if (o0 + k < H) v = load_raw<T, WT>(wres, hb, so);
+            hraw[k] = col_ok ? v : (Raw)0;
+            so += rowbytes;
           }
-        }
-        const int col = v0 + lane;
-        double sx = 0.0;
+        });
+        T a[KB], mu[KB], mv[KB];
+        if (wave == 0)
+          column_pass<T, R, 0>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+        else
+          column_pass<T, R, 1>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+        T hv[KB];
+        with_weight_type(wdtype, [&](auto wt) {
+          using WT = decltype(wt);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int o = ofirst + k;
-          if (o < seg_end && col < W) {
-            const size_t off = (size_t)o * im.map_pitch + col;
-            Aout[off] = a[k];
-            Muout[off] = mu[k];
-            Mvout[off] = mv[k];
-            sx += load_weight(wimg, wdtype, pitch, H, W, o, col, scale) * (double)a[k];
+          for (int k = 0; k < KB; ++k) hv[k] = raw_value<T, WT>(hraw[k]);
+        });
+        // rows are stored whole: the strip's 64 columns lie inside the padded
+        // map pitch, and columns past the width carry zero weight for S_X
+        T sx = (T)0;
+        uint32_t so = (uint32_t)o0 * mpb;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          if (o0 + k < seg_end) {
+            buf_store<T>(a[k], mres, mvoff, so);
+            buf_store<T>(mu[k], mres, mvoff, so + planeb);
+            buf_store<T>(mv[k], mres, mvoff, so + 2 * planeb);
+            sx = fma_t(hv[k], a[k], sx);
           }
+          so += mpb;
         }
-        sx = wave_sum(sx);
-        if (lane == 0) part[(size_t)strip * im.ngroups + ofirst / CONV_GROUP] = sx;
+        buf_store<T>(sx * scale, mres, (uint32_t)lane * (uint32_t)sizeof(T),
+                     part_base + (uint32_t)(o0 / KB) * (uint32_t)(CONV_TW * sizeof(T)));
       }
     }
   }
@@ -223,12 +357,12 @@ __global__ void __launch_bounds__(CONV_NT) conv_tiles_kernel(const ImageDesc* __
   }
 }
 
-// S_X of one image from its partials (fixed summation order).
+// S_X of one image from its partials (fixed summation order, FP64).
 template <typename T>
 __global__ void __launch_bounds__(256) sx_finalize_kernel(ImageDesc im, const char* mbase, double* s_x) {
   __shared__ double red[4];
-  const double* part = reinterpret_cast<const double*>(mbase + im.map_off + im.part_off);
-  const double s = block_sum_fixed(part, im.nstrips * im.ngroups, red);
+  const T* part = reinterpret_cast<const T*>(mbase + im.map_off + im.part_off);
+  const double s = block_sum_fixed(part, (int64_t)im.nstrips * im.ngroups * CONV_TW, red);
   if (threadIdx.x == 0) *s_x = s;
 }
 

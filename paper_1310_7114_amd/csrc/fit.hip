@@ -246,8 +246,8 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
   for (int ii = blockIdx.x; ii < fa.n; ii += gridDim.x) {
     const int i = order[ii];
     const ImageDesc im = images[i];
-    const double* part = reinterpret_cast<const double*>((const char*)fa.maps + im.map_off + im.part_off);
-    const double s_x = block_sum_fixed(part, im.nstrips * im.ngroups, red);
+    const T* part = reinterpret_cast<const T*>((const char*)fa.maps + im.map_off + im.part_off);
+    const double s_x = block_sum_fixed(part, (int64_t)im.nstrips * im.ngroups * CONV_TW, red);
     if (threadIdx.x == 0 && fa.s_x_out) fa.s_x_out[i] = s_x;
     FitImageArgs a;
     a.mbase = (const char*)fa.maps;

@@ -44,28 +44,47 @@ __device__ __forceinline__ float wave_max(float x) {
   return x;
 }
 
-// Stored weight of pixel (y, x) times the scale, in double; 0 off the lattice.
-__device__ __forceinline__ double load_weight(const char* base, int wdtype, int64_t pitch, int H,
-                                              int W, int y, int x, double scale) {
-  if (y < 0 || y >= H || x < 0 || x >= W) return 0.0;
-  const int64_t i = (int64_t)y * pitch + x;
-  double v;
-  if (wdtype == 0)
-    v = (double)((const uint8_t*)base)[i];
-  else if (wdtype == 1)
-    v = (double)((const float*)base)[i];
-  else
-    v = ((const double*)base)[i];
-  return v * scale;
+// ---------------------------------------------------------------------------
+// Buffer access: a uniform base in a resource descriptor, a per-lane 32-bit
+// byte offset and a uniform 32-bit byte offset (scalar register). Callers keep
+// every access inside [base, base + bytes); the hardware range check is not
+// relied on.
+// ---------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// Deterministic sum of n doubles by one workgroup of nt threads (nt a
-// multiple of 64): thread t adds t, t+nt, ...; then waves, then wave 0.
-// `red` is shared scratch of nt/64 doubles. Every thread gets the total.
-__device__ inline double block_sum_fixed(const double* p, int n, double* red) {
+template <typename WT>
+__device__ __forceinline__ WT buf_load(rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(WT) == 1) {
+    return (WT)__builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
+  } else if constexpr (sizeof(WT) == 4) {
+    return __builtin_bit_cast(WT, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(WT, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v),
+                                          r, voff, soff, 0);
+}
+
+// Deterministic FP64 sum of n values by one workgroup of nt threads (nt a
+// multiple of 64): thread t adds t, t+nt, ...; then each wave by a fixed xor
+// tree; then the waves in order. `red` is shared scratch of nt/64 doubles.
+// Every thread gets the total.
+template <typename P>
+__device__ inline double block_sum_fixed(const P* p, int64_t n, double* red) {
   const int nt = blockDim.x, tid = threadIdx.x;
   double s = 0.0;
-  for (int i = tid; i < n; i += nt) s += p[i];
+  for (int64_t i = tid; i < n; i += nt) s += (double)p[i];
   s = wave_sum(s);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();

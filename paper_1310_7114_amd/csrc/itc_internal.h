@@ -10,10 +10,12 @@ namespace itc {
 // Convolution geometry: a workgroup owns a strip of CONV_TW columns and a
 // segment of rows; it streams down the segment in chunks of CONV_CH rows.
 // ---------------------------------------------------------------------------
-constexpr int CONV_TW = 64;    // strip width = one wave of lanes
-constexpr int CONV_CH = 16;    // rows per chunk
-constexpr int CONV_NT = 256;   // threads per workgroup (4 waves)
-constexpr int CONV_GROUP = 4;  // rows per S_X partial (one wave's rows in a chunk)
+constexpr int CONV_TW = 64;     // strip width = one wave of lanes
+constexpr int CONV_CH = 16;     // rows per chunk
+constexpr int CONV_WAVES = 2;   // waves per workgroup, sharing one strip
+constexpr int CONV_NT = 64 * CONV_WAVES;
+constexpr int CONV_KB = CONV_CH / CONV_WAVES;  // output rows per lane per chunk
+constexpr int CONV_GROUP = CONV_KB;            // rows per S_X partial
 constexpr int ITC_MAX_CODEVECTORS_DEV = 1024;
 
 // Supported truncation radii are rounded up to one of these classes; taps
@@ -35,6 +37,8 @@ inline int radius_class(int R, bool f64) {
 inline int64_t map_pitch_of(int W) { return ((int64_t)W + 63) / 64 * 64; }
 inline int n_strips(int W) { return (W + CONV_TW - 1) / CONV_TW; }
 inline int n_groups(int H) { return (H + CONV_GROUP - 1) / CONV_GROUP; }
+// S_X partials: one per (strip, CONV_GROUP-row group, lane), in the real type.
+inline int64_t n_partials(int H, int W) { return (int64_t)n_strips(W) * n_groups(H) * CONV_TW; }
 
 // One image as the kernels see it. Offsets are in bytes from the batch bases.
 struct ImageDesc {

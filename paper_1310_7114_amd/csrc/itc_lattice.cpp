@@ -73,6 +73,14 @@ itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out) {
   if (rc < 0)
     return fail(ITC_E_UNSUPPORTED, "radius %d exceeds the compiled maximum %d for %s", R,
                 f64 ? ITC_MAX_RADIUS_F64 : ITC_MAX_RADIUS_F32, f64 ? "FP64" : "FP32");
+  // the kernels address one image and its maps with 32-bit byte offsets
+  const uint64_t esz = d->weight_dtype == ITC_U8 ? 1 : (d->weight_dtype == ITC_F32 ? 4 : 8);
+  const uint64_t img_bytes = (uint64_t)d->height * (uint64_t)d->pitch * esz;
+  const uint64_t map_bytes = (uint64_t)3 * d->height * (uint64_t)itc::map_pitch_of(d->width) * (f64 ? 8 : 4) +
+                             (uint64_t)itc::n_partials(d->height, d->width) * (f64 ? 8 : 4);
+  if (img_bytes >= (1ull << 31) || map_bytes >= (1ull << 31))
+    return fail(ITC_E_UNSUPPORTED, "image (%llu B) or maps (%llu B) exceed 2 GiB", (unsigned long long)img_bytes,
+                (unsigned long long)map_bytes);
   if (R_out) *R_out = R;
   if (rc_out) *rc_out = rc;
   return ITC_OK;
@@ -83,7 +91,7 @@ size_t planes_bytes(const itc_lattice_desc& d) {
 }
 
 size_t maps_bytes_of(const itc_lattice_desc& d) {
-  const size_t part = (size_t)itc::n_strips(d.width) * itc::n_groups(d.height) * sizeof(double);
+  const size_t part = (size_t)itc::n_partials(d.height, d.width) * real_size(d.real_dtype);
   return (planes_bytes(d) + part + 255) / 256 * 256;
 }
 

@@ -50,7 +50,7 @@ def test_sizes_and_radius(itc):
     assert lib.itc_lattice_radius(ctypes.byref(d)) == 12
     assert lib.itc_lattice_map_pitch(ctypes.byref(d)) == 192
     planes = 3 * 100 * 192 * 4
-    parts = 3 * 25 * 8
+    parts = 3 * 13 * 64 * 4    # ceil(130/64) strips x ceil(100/8) groups x 64 lanes, FP32
     assert itc.maps_bytes(d) == (planes + parts + 255) // 256 * 256
     d2 = itc.make_desc(10, 10, 2.0, radius=5)
     assert lib.itc_lattice_radius(ctypes.byref(d2)) == 5
