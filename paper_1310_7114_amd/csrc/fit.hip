@@ -1,40 +1,44 @@
 // ITC fixed-point iteration on precomputed lattice maps (eq. (4) with the data
 // sums read from the convolution maps, Section 3.1; loop of Algorithm 1).
 //
-// One 256-thread workgroup fits one image; the codebook lives in LDS (double
-// buffered, Jacobi order). Each codevector k is owned by a group of P lanes
-// (P a power of two chosen from M so that the M x M work is spread over the
-// workgroup): the P lanes share the bilinear map reads at w_k and split the
-// sum over j of the codebook Gaussian terms, which they then combine with a
-// fixed xor-shuffle tree. S_XW = sum_k A_k and S_W = sum_k C_k are reduced in
-// FP64 in a fixed order, so results are bitwise reproducible and identical
-// between the single-image and the batched launch.
+// One 256-thread workgroup fits one image. Each codevector k is owned by a
+// group of P lanes (P a power of two chosen from M, a template parameter so
+// the pair loop unrolls with immediate LDS offsets): the P lanes read the maps
+// bilinearly at w_k and split the sum over j of the codebook Gaussian terms,
+// which they combine with a fixed cross-lane (DPP) tree. S_XW = sum_k A_k and
+// S_W = sum_k C_k are reduced in FP64 in a fixed order, so results are
+// bitwise reproducible and identical between the single-image and the
+// batched launch.
 //
-// Codevector positions are held in FP64 whatever the map type: with FP32
-// coordinates the rounding of w (2.4e-4 px at u ~ 2048) and of the pair
-// differences w_j - w_k would dominate the error of the iteration. The
-// differences and bilinear fractions are formed in FP64 and rounded once to
-// the map type, in which the Gaussians and sums are evaluated.
+// Precision: codevector positions are FP64 whatever the map type (with FP32
+// coordinates the rounding of w, 2.4e-4 px near u = 2048, would dominate the
+// error). Owners keep their positions in registers; LDS holds a copy scaled
+// by s = sqrt(log2(e) / (2 sigma^2)), so that a pair's Gaussian is
+// exp2(-|w_j' - w_k'|^2) and its repulsion sum is E = E'/s. Pair differences
+// are formed in FP64 and rounded once to the map type, in which the
+// Gaussians and sums are evaluated. The LDS codebook is padded to a multiple
+// of 4P with points at 1e30, whose Gaussian is exactly 0.
 #include "itc_device.h"
 
 namespace itc {
 
 constexpr int FIT_NT = 256;
 constexpr int FIT_MAXPASS = ITC_MAX_CODEVECTORS_DEV / FIT_NT;
+constexpr double FIT_FAR = 1e30;
 
 template <typename T>
 struct V2 {
   T u, v;
 };
+using P2 = V2<double>;
 
-__device__ __forceinline__ float gauss_unit(float d2, float k2) {
-  // exp(-d2 / (2 sigma^2)) = 2^(-d2 * k2), k2 = log2(e) / (2 sigma^2)
-  return __builtin_amdgcn_exp2f(-d2 * k2);
-}
-__device__ __forceinline__ double gauss_unit(double d2, double k2) { return exp2(-d2 * k2); }
+__device__ __forceinline__ float exp2_neg(float x) { return __builtin_amdgcn_exp2f(-x); }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double exp2_neg(double x) { return exp2(-x); }
 
 // Lanes per codevector: minimise passes * ceil(M / P) with at most FIT_MAXPASS passes.
-__device__ __forceinline__ int lanes_per_codevector(int M) {
+__host__ __device__ inline int lanes_per_codevector(int M) {
   int bestP = 1, best = 1 << 30;
   for (int P = 1; P <= 64; P <<= 1) {
     const int slots = FIT_NT / P;
@@ -49,6 +53,8 @@ __device__ __forceinline__ int lanes_per_codevector(int M) {
   return bestP;
 }
 
+__host__ __device__ inline int padded_codebook(int M, int P) { return (M + 4 * P - 1) / (4 * P) * (4 * P); }
+
 struct FitImageArgs {
   const char* mbase;
   const void* w_init;
@@ -61,38 +67,50 @@ struct FitImageArgs {
   bool write_w;
 };
 
-template <typename T>
+template <typename T, int P>
 __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem) {
+  constexpr int SLOTS = FIT_NT / P;
   const int M = im.M;
+  const int Mpad = padded_codebook(M, P);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  using P2 = V2<double>;
-  P2* Wa = reinterpret_cast<P2*>(smem);
-  P2* Wb = Wa + M;
-  double* red = reinterpret_cast<double*>(Wb + M);  // [4 waves][2]
-  double* red2 = red + 8;                           // [4 waves]
+  const int grp = tid / P, p = tid % P;
+  const int npass = (M + SLOTS - 1) / SLOTS;
+  P2* Wh = reinterpret_cast<P2*>(smem);                // scaled positions [Mpad]
+  double* red = reinterpret_cast<double*>(Wh + Mpad);  // [4 waves][2]
+  double* red2 = red + 8;                              // [4 waves]
 
+  const double s = sqrt(1.4426950408889634 / (2.0 * im.sigma * im.sigma));
   const V2<T>* w_in = reinterpret_cast<const V2<T>*>(a.w_init) + im.w_off;
-  for (int k = tid; k < M; k += FIT_NT) {
-    const V2<T> w = w_in[k];
-    Wa[k] = P2{(double)w.u, (double)w.v};
+
+  // owned codevectors (FP64, in registers; identical in all P lanes of a group)
+  double wu[FIT_MAXPASS], wv[FIT_MAXPASS];
+#pragma unroll
+  for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+    const int k = ps * SLOTS + grp;
+    wu[ps] = wv[ps] = 0.0;
+    if (ps < npass && k < M) {
+      const V2<T> w = w_in[k];
+      wu[ps] = (double)w.u;
+      wv[ps] = (double)w.v;
+    }
+  }
+  for (int k = tid; k < Mpad; k += FIT_NT) {
+    P2 h{FIT_FAR, FIT_FAR};
+    if (k < M) {
+      const V2<T> w = w_in[k];
+      h = P2{s * (double)w.u, s * (double)w.v};
+    }
+    Wh[k] = h;
   }
   __syncthreads();
 
   const int H = im.H, W = im.W;
-  const int64_t mp = im.map_pitch;
-  const T* Ap = reinterpret_cast<const T*>(a.mbase + im.map_off);
-  const T* Mup = Ap + (size_t)H * mp;
-  const T* Mvp = Mup + (size_t)H * mp;
-
-  const int P = lanes_per_codevector(M);
-  const int slots = FIT_NT / P;
-  const int npass = (M + slots - 1) / slots;
-  const int grp = tid / P, p = tid % P;
-  const T k2 = (T)(1.4426950408889634 / (2.0 * im.sigma * im.sigma));
+  const int mpl = (int)im.map_pitch;
+  const uint32_t planeb = (uint32_t)H * (uint32_t)mpl * (uint32_t)sizeof(T);
+  const rsrc_t mres = make_rsrc(a.mbase + im.map_off, 3u * planeb);
   const bool need_d = a.d_trace != nullptr || a.d_out != nullptr;
+  const P2* wcol = Wh + p;  // this lane's column of the pair loop: j = p + P t
 
-  P2* Wc = Wa;
-  P2* Wn = Wb;
   bool stop = false;
   int t = 0;
   for (;; ++t) {
@@ -105,48 +123,64 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
       Ak[ps] = gu[ps] = gv[ps] = Eu[ps] = Ev[ps] = (T)0;
       if (ps < npass) {
-        const int k = ps * slots + grp;
+        const int k = ps * SLOTS + grp;
         const bool own = k < M;
-        const P2 wk = Wc[own ? k : 0];
-        // ---- data terms: bilinear read of A, M_u, M_v at w_k ----
-        T A = 0, Gu = 0, Gv = 0;
-        if (own && wk.u > -1.0 && wk.u < (double)H && wk.v > -1.0 && wk.v < (double)W) {
-          const double fu0 = floor(wk.u), fv0 = floor(wk.v);
+        const double uk = wu[ps], vk = wv[ps];
+        // ---- data terms: bilinear read of A, M_u, M_v at w_k. The 12 loads are
+        // issued here and consumed after the pair loop, which hides their latency.
+        // Off-lattice corners load a clamped in-bounds element and are zeroed.
+        T fu = 0, fv = 0;
+        T av[4], mu[4], mv[4];
+        {
+          const bool inside = own && uk > -1.0 && uk < (double)H && vk > -1.0 && vk < (double)W;
+          const double fu0 = inside ? floor(uk) : 0.0, fv0 = inside ? floor(vk) : 0.0;
           const int i0 = (int)fu0, j0 = (int)fv0;
-          const T fu = (T)(wk.u - fu0), fv = (T)(wk.v - fv0);
+          fu = (T)(uk - fu0);
+          fv = (T)(vk - fv0);
+          const bool r0 = inside && i0 >= 0, r1 = inside && i0 + 1 < H;
+          const bool c0 = j0 >= 0, c1 = j0 + 1 < W;
+          const uint32_t base = (uint32_t)(i0 * mpl + j0) * (uint32_t)sizeof(T);
 #pragma unroll
-          for (int di = 0; di < 2; ++di) {
+          for (int c = 0; c < 4; ++c) {
+            const int di = c >> 1, dj = c & 1;
+            const bool ok = (di ? r1 : r0) && (dj ? c1 : c0);
+            const uint32_t off = ok ? base + (uint32_t)(di * mpl + dj) * (uint32_t)sizeof(T) : 0u;
+            const T x0 = buf_load<T>(mres, off, 0);
+            const T x1 = buf_load<T>(mres, off, planeb);
+            const T x2 = buf_load<T>(mres, off, 2 * planeb);
+            av[c] = ok ? x0 : (T)0;
+            mu[c] = ok ? x1 : (T)0;
+            mv[c] = ok ? x2 : (T)0;
+          }
+        }
+        // ---- codebook terms over j = p, p + P, ... (scaled coordinates) ----
+        T C = 0, Cu = 0, Cv = 0;
+        if (own) {
+          const double hu = s * uk, hv = s * vk;
+          for (int jt = 0; jt < Mpad; jt += 4 * P) {
 #pragma unroll
-            for (int dj = 0; dj < 2; ++dj) {
-              const int i = i0 + di, j = j0 + dj;
-              if (i >= 0 && i < H && j >= 0 && j < W) {
-                const T b = (di ? fu : (T)1 - fu) * (dj ? fv : (T)1 - fv);
-                const size_t off = (size_t)i * mp + j;
-                const T av = Ap[off], mu = Mup[off], mv = Mvp[off];
-                A = fma_t(b, av, A);
-                // (c - w_k) A(c) - M(c) with c - w_k = (di - fu, dj - fv)
-                Gu = fma_t(b, fma_t((T)di - fu, av, -mu), Gu);
-                Gv = fma_t(b, fma_t((T)dj - fv, av, -mv), Gv);
-              }
+            for (int u = 0; u < 4; ++u) {
+              const P2 wj = wcol[jt + u * P];
+              const T du = (T)(wj.u - hu), dv = (T)(wj.v - hv);
+              const T e = exp2_neg(fma_t(du, du, dv * dv));
+              C += e;
+              Cu = fma_t(e, du, Cu);
+              Cv = fma_t(e, dv, Cv);
             }
           }
         }
-        // ---- codebook terms over j = p, p + P, ... ----
-        T C = 0, Cu = 0, Cv = 0;
-        if (own) {
-          for (int j = p; j < M; j += P) {
-            const P2 wj = Wc[j];
-            const T du = (T)(wj.u - wk.u), dv = (T)(wj.v - wk.v);
-            const T e = gauss_unit(fma_t(du, du, dv * dv), k2);
-            C += e;
-            Cu = fma_t(e, du, Cu);
-            Cv = fma_t(e, dv, Cv);
-          }
-        }
-        for (int m = P >> 1; m >= 1; m >>= 1) {
-          C += __shfl_xor(C, m, 64);
-          Cu += __shfl_xor(Cu, m, 64);
-          Cv += __shfl_xor(Cv, m, 64);
+        C = group_sum<P>(C);
+        Cu = group_sum<P>(Cu);
+        Cv = group_sum<P>(Cv);
+        // bilinear combination: A = sum_c b_c A(c), g = sum_c b_c ((c - w_k) A(c) - M(c))
+        T A = 0, Gu = 0, Gv = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int di = c >> 1, dj = c & 1;
+          const T b = (di ? fu : (T)1 - fu) * (dj ? fv : (T)1 - fv);
+          A = fma_t(b, av[c], A);
+          Gu = fma_t(b, fma_t((T)di - fu, av[c], -mu[c]), Gu);
+          Gv = fma_t(b, fma_t((T)dj - fv, av[c], -mv[c]), Gv);
         }
         Ak[ps] = A;
         gu[ps] = Gu;
@@ -173,53 +207,67 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       S_XW += red[2 * w];
       S_W += red[2 * w + 1];
     }
-    if (need_d) {
+    if (tid == 0 && (a.d_trace || (last && a.d_out))) {
       const double D = log(S_W) + log(a.s_x) - 2.0 * log(S_XW);
-      if (tid == 0) {
-        if (a.d_trace) a.d_trace[t] = D;
-        if (last && a.d_out) *a.d_out = D;
-      }
+      if (a.d_trace) a.d_trace[t] = D;
+      if (last && a.d_out) *a.d_out = D;
     }
     if (last) break;
 
-    // ---- Jacobi update of every owned codevector ----
-    const T c = (T)(S_XW / S_W);
+    // ---- Jacobi update of every owned codevector (all P lanes alike) ----
+    const T cs = (T)(S_XW / S_W / s);  // c / s: E = E' / s
     float step = 0.0f;
 #pragma unroll
     for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
       if (ps < npass) {
-        const int k = ps * slots + grp;
-        if (k < M && p == 0) {
-          P2 w = Wc[k];
-          if (Ak[ps] != (T)0) {
-            const T du = (gu[ps] - c * Eu[ps]) / Ak[ps];
-            const T dv = (gv[ps] - c * Ev[ps]) / Ak[ps];
-            w.u += (double)du;
-            w.v += (double)dv;
-            step = fmaxf(step, (float)sqrt((double)du * du + (double)dv * dv));
-          }
-          Wn[k] = w;
+        const int k = ps * SLOTS + grp;
+        if (k < M && Ak[ps] != (T)0) {
+          const T inv = recip(Ak[ps]);
+          const T du = (gu[ps] - cs * Eu[ps]) * inv;
+          const T dv = (gv[ps] - cs * Ev[ps]) * inv;
+          wu[ps] += (double)du;
+          wv[ps] += (double)dv;
+          if (a.theta >= 0.0) step = fmaxf(step, (float)sqrt((double)du * du + (double)dv * dv));
+          if (p == 0) Wh[k] = P2{s * wu[ps], s * wv[ps]};
         }
       }
     }
-    step = wave_max(step);
-    if (lane == 0) red2[wave] = (double)step;
+    if (a.theta >= 0.0) {  // the largest step is needed only for the theta test
+      step = wave_max_nonneg(step);
+      if (lane == 0) red2[wave] = (double)step;
+    }
     __syncthreads();
-    double smax = 0.0;
+    if (a.theta >= 0.0) {
+      double smax = 0.0;
 #pragma unroll
-    for (int w = 0; w < FIT_NT / 64; ++w) smax = fmax(smax, red2[w]);
-    stop = a.theta >= 0.0 && smax <= a.theta;
-    P2* tmp = Wc;
-    Wc = Wn;
-    Wn = tmp;
+      for (int w = 0; w < FIT_NT / 64; ++w) smax = fmax(smax, red2[w]);
+      stop = smax <= a.theta;
+    }
   }
 
   if (a.write_w) {
     V2<T>* w_o = reinterpret_cast<V2<T>*>(a.w_out) + im.w_off;
-    for (int k = tid; k < M; k += FIT_NT) w_o[k] = V2<T>{(T)Wc[k].u, (T)Wc[k].v};
+#pragma unroll
+    for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+      const int k = ps * SLOTS + grp;
+      if (ps < npass && k < M && p == 0) w_o[k] = V2<T>{(T)wu[ps], (T)wv[ps]};
+    }
   }
   if (tid == 0 && a.iters_done) *a.iters_done = t;
   __syncthreads();  // shared memory is reused by the next image
+}
+
+template <typename T>
+__device__ __forceinline__ void fit_dispatch(const ImageDesc& im, const FitImageArgs& a, char* smem) {
+  switch (lanes_per_codevector(im.M)) {
+    case 1: fit_image<T, 1>(im, a, smem); break;
+    case 2: fit_image<T, 2>(im, a, smem); break;
+    case 4: fit_image<T, 4>(im, a, smem); break;
+    case 8: fit_image<T, 8>(im, a, smem); break;
+    case 16: fit_image<T, 16>(im, a, smem); break;
+    case 32: fit_image<T, 32>(im, a, smem); break;
+    default: fit_image<T, 64>(im, a, smem); break;
+  }
 }
 
 template <typename T>
@@ -235,7 +283,7 @@ __global__ void __launch_bounds__(FIT_NT) fit_image_kernel(ImageDesc im, FitArgs
   a.iters_done = fa.iters_done;
   a.theta = fa.theta;
   a.write_w = fa.write_w != 0;
-  fit_image<T>(im, a, smem);
+  fit_dispatch<T>(im, a, smem);
 }
 
 template <typename T>
@@ -259,21 +307,24 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
     a.iters_done = fa.iters_done ? fa.iters_done + i : nullptr;
     a.theta = fa.theta;
     a.write_w = fa.write_w != 0;
-    fit_image<T>(im, a, smem);
+    fit_dispatch<T>(im, a, smem);
   }
 }
 
-template <typename T>
+// Shared memory of the fit for codebooks up to m_max: the padded scaled
+// codebook (largest over every P) plus the reduction scratch.
 static size_t fit_smem(int m_max) {
-  return (size_t)2 * m_max * sizeof(V2<double>) + 12 * sizeof(double) + 64;
+  int mp = 0;
+  for (int P = 1; P <= 64; P <<= 1) mp = mp > padded_codebook(m_max, P) ? mp : padded_codebook(m_max, P);
+  return (size_t)mp * sizeof(P2) + 12 * sizeof(double) + 64;
 }
 
 int fit_blocks_per_cu(bool f64, int m_max) {
   int nb = 0;
   hipError_t e = f64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_batched_kernel<double>, FIT_NT,
-                                                                    fit_smem<double>(m_max))
+                                                                    fit_smem(m_max))
                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_batched_kernel<float>, FIT_NT,
-                                                                    fit_smem<float>(m_max));
+                                                                    fit_smem(m_max));
   return e == hipSuccess ? nb : 0;
 }
 
@@ -281,19 +332,17 @@ hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_orde
                       int grid, hipStream_t s, const ImageDesc* h_image) {
   if (h_image) {
     if (f64)
-      hipLaunchKernelGGL(fit_image_kernel<double>, dim3(1), dim3(FIT_NT), fit_smem<double>(h_image->M), s,
-                         *h_image, a);
+      hipLaunchKernelGGL(fit_image_kernel<double>, dim3(1), dim3(FIT_NT), fit_smem(h_image->M), s, *h_image, a);
     else
-      hipLaunchKernelGGL(fit_image_kernel<float>, dim3(1), dim3(FIT_NT), fit_smem<float>(h_image->M), s,
-                         *h_image, a);
+      hipLaunchKernelGGL(fit_image_kernel<float>, dim3(1), dim3(FIT_NT), fit_smem(h_image->M), s, *h_image, a);
     return hipGetLastError();
   }
   if (f64)
-    hipLaunchKernelGGL(fit_batched_kernel<double>, dim3(grid), dim3(FIT_NT), fit_smem<double>(a.m_max), s,
-                       d_images, d_order, a);
+    hipLaunchKernelGGL(fit_batched_kernel<double>, dim3(grid), dim3(FIT_NT), fit_smem(a.m_max), s, d_images,
+                       d_order, a);
   else
-    hipLaunchKernelGGL(fit_batched_kernel<float>, dim3(grid), dim3(FIT_NT), fit_smem<float>(a.m_max), s,
-                       d_images, d_order, a);
+    hipLaunchKernelGGL(fit_batched_kernel<float>, dim3(grid), dim3(FIT_NT), fit_smem(a.m_max), s, d_images,
+                       d_order, a);
   return hipGetLastError();
 }
 

@@ -32,16 +32,66 @@ __device__ __forceinline__ double lane_value(double x, int l) {
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Sum over the 64 lanes of a wave by a fixed xor tree (same order every call).
+// Cross-lane moves through DPP (data-parallel primitives of the VALU): no LDS
+// round trip, so a whole-wave reduction costs a few VALU latencies.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_f64(double x) {
+  int2 v = __builtin_bit_cast(int2, x);
+  v.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, ROWS, 0xf, false);
+  v.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, v);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
+}
+// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror,
+// row_mirror, row_bcast:15 (into rows 1 and 3), row_bcast:31 (into rows 2, 3).
+constexpr int DPP_QP_1032 = 0xb1, DPP_QP_2301 = 0x4e, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140,
+              DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
+// Sum over the 64 lanes of a wave in a fixed order; every lane gets it.
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  x += dpp_f64<DPP_QP_1032>(x);
+  x += dpp_f64<DPP_QP_2301>(x);
+  x += dpp_f64<DPP_HALF_MIRROR>(x);
+  x += dpp_f64<DPP_MIRROR>(x);
+  x += dpp_f64<DPP_BCAST15, 0xa>(x);
+  x += dpp_f64<DPP_BCAST31, 0xc>(x);
+  return lane_value(x, 63);
+}
+// Sum over aligned groups of P lanes (P a power of two); every lane of a group
+// gets the same value (each step adds a commutative pair).
+template <int P>
+__device__ __forceinline__ float group_sum(float x) {
+  if constexpr (P >= 2) x += dpp_f32<DPP_QP_1032>(x);
+  if constexpr (P >= 4) x += dpp_f32<DPP_QP_2301>(x);
+  if constexpr (P >= 8) x += dpp_f32<DPP_HALF_MIRROR>(x);
+  if constexpr (P >= 16) x += dpp_f32<DPP_MIRROR>(x);
+  if constexpr (P >= 32) x += __shfl_xor(x, 16, 64);
+  if constexpr (P >= 64) x += __shfl_xor(x, 32, 64);
   return x;
 }
-__device__ __forceinline__ float wave_max(float x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = fmaxf(x, __shfl_xor(x, m, 64));
+template <int P>
+__device__ __forceinline__ double group_sum(double x) {
+  if constexpr (P >= 2) x += dpp_f64<DPP_QP_1032>(x);
+  if constexpr (P >= 4) x += dpp_f64<DPP_QP_2301>(x);
+  if constexpr (P >= 8) x += dpp_f64<DPP_HALF_MIRROR>(x);
+  if constexpr (P >= 16) x += dpp_f64<DPP_MIRROR>(x);
+  if constexpr (P >= 32) x += __shfl_xor(x, 16, 64);
+  if constexpr (P >= 64) x += __shfl_xor(x, 32, 64);
   return x;
+}
+
+// Max over the 64 lanes of a wave of non-negative values; every lane gets it.
+__device__ __forceinline__ float wave_max_nonneg(float x) {
+  x = fmaxf(x, dpp_f32<DPP_QP_1032>(x));
+  x = fmaxf(x, dpp_f32<DPP_QP_2301>(x));
+  x = fmaxf(x, dpp_f32<DPP_HALF_MIRROR>(x));
+  x = fmaxf(x, dpp_f32<DPP_MIRROR>(x));
+  x = fmaxf(x, dpp_f32<DPP_BCAST15, 0xa>(x));
+  x = fmaxf(x, dpp_f32<DPP_BCAST31, 0xc>(x));
+  return lane_value(x, 63);
 }
 
 // ---------------------------------------------------------------------------
