@@ -149,7 +149,8 @@ itc_status itc_lattice_divergence(const itc_lattice_desc* d, const void* maps, c
  *   K(y) = sum_k sum_c beta_kc g(c - y)   (bilinear corner weights of w_k, window R)
  * grad_w is [M][2] in the real type; grad_weights is height x width, row pitch
  * `width`, in the real type, the derivative with respect to the weight
- * h = weight_scale * stored. Either output may be NULL to skip it.
+ * h = weight_scale * stored. Either output may be NULL to skip it; `s_x`
+ * (from precompute) is required for grad_weights.
  */
 itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void* maps,
                                            const double* s_x, int32_t M, const void* w,
@@ -197,6 +198,19 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
 itc_status itc_lattice_run_batched(itc_plan* p, const void* weights, void* maps, const void* w_init,
                                    double theta, void* w_out, double* s_x, double* d_out,
                                    int32_t* iters_done, void* stream);
+
+/*
+ * Adjoint of the divergence of every image at codebooks `w` (same layout as
+ * w_init), as itc_lattice_divergence_backward does for one image. `s_x` and
+ * `grad_d` are double [n] (S_X of each image as written by the batched fit,
+ * and dL/dD per image). grad_w has the codebook layout; grad_weights holds
+ * image i's height x width gradient (row pitch width, real type) starting at
+ * element offset weight_off[i] / sizeof(stored weight). Either output may be
+ * NULL; s_x may be NULL when grad_weights is.
+ */
+itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps, const double* s_x,
+                                                   const void* w, const double* grad_d, void* grad_w,
+                                                   void* grad_weights, void* stream);
 
 /* Number of images in the plan, or -1 for NULL. */
 int32_t itc_lattice_plan_size(const itc_plan* p);

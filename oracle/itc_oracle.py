@@ -50,7 +50,7 @@ __all__ = [
     "parzen_gauss", "widths", "overlap_xw", "overlap_w", "overlap_x", "cs_divergence",
     "original_terms", "original_step", "original_divergence", "original_grad_w",
     "original_grad_h", "fit_original",
-    "taps", "correlate_axis", "lattice_maps", "lattice_maps_window", "moment_maps",
+    "taps", "correlate_axis", "lattice_maps", "density_map", "lattice_maps_window", "moment_maps",
     "read_bilinear", "read_nearest", "read_bilinear_grad", "codebook_terms",
     "lattice_step", "lattice_divergence", "lattice_grad", "fit_lattice",
 ]
@@ -276,6 +276,12 @@ def lattice_maps(I: np.ndarray, sigma: float, R: int):
     return tuple(out)
 
 
+def density_map(I: np.ndarray, sigma: float, R: int) -> np.ndarray:
+    """A(x) = sum_y I(y) g(x - y) alone (the P = X * G density of Algorithm 1)."""
+    g = taps(sigma, R)
+    return correlate_axis(correlate_axis(np.asarray(I, np.float64), g, 1), g, 0)
+
+
 def lattice_maps_window(I: np.ndarray, sigma: float, R: int):
     """The same three maps as a direct 2-D window sum over all (du, dv) offsets."""
     I = np.asarray(I, np.float64)
@@ -395,7 +401,7 @@ def lattice_step(maps, W, sigma, read="bilinear"):
 def lattice_divergence(I, maps, W, sigma, read="bilinear", s_x=None):
     """Eq. (1) with lattice sums: V(X;W) from the map reads, V(X) = sum I A.
 
-    All three overlaps carry the same normalisation 1/(2 pi sigma^2) and the
+    Only the density map A = maps[0] is used. All three overlaps carry the same normalisation 1/(2 pi sigma^2) and the
     same 1/N, 1/M factors as in Section 2.1, written out here.
     """
     I = np.asarray(I, np.float64)
@@ -403,7 +409,7 @@ def lattice_divergence(I, maps, W, sigma, read="bilinear", s_x=None):
     W = np.asarray(W, np.float64)
     N, M = float(I.sum()), W.shape[0]
     Z = 1.0 / (2.0 * math.pi * sigma * sigma)
-    den, _ = _reads(maps, W, read)
+    den = (read_bilinear if read == "bilinear" else read_nearest)(A, W)
     C, _ = codebook_terms(W, sigma)
     if s_x is None:
         s_x = float(np.sum(I * A))

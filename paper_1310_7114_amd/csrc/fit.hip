@@ -26,10 +26,6 @@ constexpr int FIT_NT = 256;
 constexpr int FIT_MAXPASS = ITC_MAX_CODEVECTORS_DEV / FIT_NT;
 constexpr double FIT_FAR = 1e30;
 
-template <typename T>
-struct V2 {
-  T u, v;
-};
 using P2 = V2<double>;
 
 __device__ __forceinline__ float exp2_neg(float x) { return __builtin_amdgcn_exp2f(-x); }
@@ -65,6 +61,8 @@ struct FitImageArgs {
   int32_t* iters_done;
   double theta;
   bool write_w;
+  void* grad_w;          // gradient mode: dL/dw [M][2] at w_init (no update)
+  const double* grad_d;  // dL/dD (one double), gradient mode only
 };
 
 template <typename T, int P>
@@ -115,13 +113,14 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   int t = 0;
   for (;; ++t) {
     const bool last = (t == im.iters) || stop;
-    if (last && !need_d) break;
+    if (last && !need_d && !a.grad_w) break;
 
     T Ak[FIT_MAXPASS], gu[FIT_MAXPASS], gv[FIT_MAXPASS], Eu[FIT_MAXPASS], Ev[FIT_MAXPASS];
+    T dAu[FIT_MAXPASS], dAv[FIT_MAXPASS];  // slope of the bilinear interpolant of A at w_k
     double sxw = 0.0, sw = 0.0;
 #pragma unroll
     for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
-      Ak[ps] = gu[ps] = gv[ps] = Eu[ps] = Ev[ps] = (T)0;
+      Ak[ps] = gu[ps] = gv[ps] = Eu[ps] = Ev[ps] = dAu[ps] = dAv[ps] = (T)0;
       if (ps < npass) {
         const int k = ps * SLOTS + grp;
         const bool own = k < M;
@@ -182,6 +181,9 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
           Gu = fma_t(b, fma_t((T)di - fu, av[c], -mu[c]), Gu);
           Gv = fma_t(b, fma_t((T)dj - fv, av[c], -mv[c]), Gv);
         }
+        // d/du and d/dv of sum_c b_c A(c): corners c = (di, dj) in (0,0),(0,1),(1,0),(1,1)
+        dAu[ps] = ((T)1 - fv) * (av[2] - av[0]) + fv * (av[3] - av[1]);
+        dAv[ps] = ((T)1 - fu) * (av[1] - av[0]) + fu * (av[3] - av[2]);
         Ak[ps] = A;
         gu[ps] = Gu;
         gv[ps] = Gv;
@@ -211,6 +213,19 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       const double D = log(S_W) + log(a.s_x) - 2.0 * log(S_XW);
       if (a.d_trace) a.d_trace[t] = D;
       if (last && a.d_out) *a.d_out = D;
+    }
+    if (a.grad_w) {  // adjoint of D at this codebook (eq. (1) differentiated through the reads)
+      const double gd = *a.grad_d;
+      const T ca = (T)(-2.0 * gd / S_XW);
+      const T cb = (T)(2.0 * gd / (im.sigma * im.sigma * S_W) / s);  // E = E'/s
+      V2<T>* gw = reinterpret_cast<V2<T>*>(a.grad_w) + im.w_off;
+#pragma unroll
+      for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+        const int k = ps * SLOTS + grp;
+        if (ps < npass && k < M && p == 0)
+          gw[k] = V2<T>{fma_t(ca, dAu[ps], cb * Eu[ps]), fma_t(ca, dAv[ps], cb * Ev[ps])};
+      }
+      break;
     }
     if (last) break;
 
@@ -283,6 +298,8 @@ __global__ void __launch_bounds__(FIT_NT) fit_image_kernel(ImageDesc im, FitArgs
   a.iters_done = fa.iters_done;
   a.theta = fa.theta;
   a.write_w = fa.write_w != 0;
+  a.grad_w = fa.grad_w;
+  a.grad_d = fa.grad_d;
   fit_dispatch<T>(im, a, smem);
 }
 
@@ -295,7 +312,7 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
     const int i = order[ii];
     const ImageDesc im = images[i];
     const T* part = reinterpret_cast<const T*>((const char*)fa.maps + im.map_off + im.part_off);
-    const double s_x = block_sum_fixed(part, (int64_t)im.nstrips * im.ngroups * CONV_TW, red);
+    const double s_x = fa.s_x_in ? fa.s_x_in[i] : block_sum_fixed(part, (int64_t)im.nstrips * im.ngroups * CONV_TW, red);
     if (threadIdx.x == 0 && fa.s_x_out) fa.s_x_out[i] = s_x;
     FitImageArgs a;
     a.mbase = (const char*)fa.maps;
@@ -307,6 +324,8 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
     a.iters_done = fa.iters_done ? fa.iters_done + i : nullptr;
     a.theta = fa.theta;
     a.write_w = fa.write_w != 0;
+    a.grad_w = fa.grad_w;
+    a.grad_d = fa.grad_d ? fa.grad_d + i : nullptr;
     fit_dispatch<T>(im, a, smem);
   }
 }

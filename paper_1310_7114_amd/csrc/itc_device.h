@@ -8,6 +8,12 @@
 
 namespace itc {
 
+// A lattice position (u = row, v = column).
+template <typename T>
+struct V2 {
+  T u, v;
+};
+
 // Scalar-register copy of a wave-uniform value.
 __device__ __forceinline__ float to_sgpr(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));

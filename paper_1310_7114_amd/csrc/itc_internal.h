@@ -17,6 +17,7 @@ constexpr int CONV_NT = 64 * CONV_WAVES;
 constexpr int CONV_KB = CONV_CH / CONV_WAVES;  // output rows per lane per chunk
 constexpr int CONV_GROUP = CONV_KB;            // rows per S_X partial
 constexpr int ITC_MAX_CODEVECTORS_DEV = 1024;
+constexpr int MAX_RADIUS = 32;
 
 // Supported truncation radii are rounded up to one of these classes; taps
 // beyond the true radius are zero, which leaves every sum unchanged.
@@ -97,22 +98,33 @@ struct FitArgs {
   int32_t n;             // images
   int32_t m_max;         // largest M (sizes the shared memory)
   int32_t write_w;       // 0: do not write w_out (divergence only)
+  void* grad_w;          // non-null: gradient mode, dL/dw at w_init (same layout), no update
+  const double* grad_d;  // gradient mode: dL/dD per image
 };
 
 hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
                       int grid, hipStream_t s, const ImageDesc* h_image);
 
-struct BackwardArgs {
-  const void* maps;
-  const void* w;
-  const double* s_x;
-  const double* grad_d;
-  void* grad_w;          // [M][2] or null
-  void* grad_weights;    // H x W or null
-  int32_t n;
+// dL/dh over one 64 x 64 pixel tile of an image.
+struct GradTile {
+  int32_t img;
+  int32_t u0, v0;
+  int32_t pad_;
 };
 
-hipError_t launch_backward(bool f64, const ImageDesc* d_images, const BackwardArgs& a, int grid_w,
-                           hipStream_t s, const ImageDesc* h_image);
+struct GradIArgs {
+  const void* maps;
+  const void* w;          // codebooks (batch base)
+  const double* s_x;      // [n] (single image: [1])
+  const double* grad_d;   // [n]
+  void* grad_weights;     // gradients in the real type at each image's weight element offset
+  int32_t m_max;
+};
+
+// Single image when h_image is non-null (grid covers its tiles), else a
+// persistent launch over `ntiles` tiles.
+hipError_t launch_grad_weights(bool f64, const ImageDesc* d_images, const GradTile* d_tiles, int ntiles,
+                               const GradIArgs& a, int grid, hipStream_t s, const ImageDesc* h_image);
+int grad_tiles_of(int H, int W);  // tiles per image
 
 }  // namespace itc

@@ -137,9 +137,12 @@ struct itc_plan {
   std::vector<int> cls, cls_begin, cls_end, cls_grid;
   std::vector<int32_t> order;  // fit order, most expensive first
   int fit_grid = 1;
+  std::vector<itc::GradTile> gtiles;  // 64 x 64 tiles of every image, for dL/dh
+  int grad_grid = 1;
   ImageDesc* d_images = nullptr;
   ConvTile* d_tiles = nullptr;
   int32_t* d_order = nullptr;
+  itc::GradTile* d_gtiles = nullptr;
 };
 
 extern "C" {
@@ -244,8 +247,42 @@ itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void
   int R = 0, rc = 0;
   itc_status st = check_desc(d, &R, &rc);
   if (st != ITC_OK) return st;
-  (void)maps; (void)s_x; (void)M; (void)w; (void)grad_d; (void)grad_w; (void)grad_weights; (void)stream;
-  return fail(ITC_E_UNSUPPORTED, "divergence backward is not built yet");
+  if (!maps || !w || !grad_d) return fail(ITC_E_NULL, "maps, w and grad_d must be non-NULL");
+  if (grad_weights && !s_x) return fail(ITC_E_NULL, "s_x is required for grad_weights");
+  if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
+  if (M > ITC_MAX_CODEVECTORS) return fail(ITC_E_UNSUPPORTED, "M %d exceeds %d", M, ITC_MAX_CODEVECTORS);
+  if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  const bool f64 = d->real_dtype == ITC_F64;
+  ImageDesc im = make_image(*d, R, rc);
+  im.M = M;
+  im.iters = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (grad_w) {
+    itc::FitArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.maps = maps;
+    a.w_init = w;
+    a.theta = -1.0;
+    a.n = 1;
+    a.m_max = M;
+    a.grad_w = grad_w;
+    a.grad_d = grad_d;
+    hipError_t e = itc::launch_fit(f64, nullptr, nullptr, a, 1, s, &im);
+    if (e != hipSuccess) return device_fail(e, "codebook gradient launch");
+  }
+  if (grad_weights) {
+    itc::GradIArgs g;
+    std::memset(&g, 0, sizeof g);
+    g.maps = maps;
+    g.w = w;
+    g.s_x = s_x;
+    g.grad_d = grad_d;
+    g.grad_weights = grad_weights;
+    g.m_max = M;
+    hipError_t e = itc::launch_grad_weights(f64, nullptr, nullptr, 0, g, 0, s, &im);
+    if (e != hipSuccess) return device_fail(e, "weight gradient launch");
+  }
+  return ok();
 }
 
 // ---------------------------------------------------------------------------
@@ -310,6 +347,8 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
       }
     }
     fit_cost[i] = (double)(im.iters + 1) * im.M * (im.M + 16.0);
+    for (int u0 = 0; u0 < im.H; u0 += 64)
+      for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
   }
   for (int rc = 0; rc < 64; ++rc) {
     if (by_class[rc].empty()) continue;
@@ -334,6 +373,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   int fper = itc::fit_blocks_per_cu(false, p->m_max);
   if (fper < 1) fper = 1;
   p->fit_grid = std::min(p->n, fper * cus);
+  p->grad_grid = std::min((int)p->gtiles.size(), 4 * cus);
 
   hipError_t e = hipMalloc(&p->d_images, sizeof(ImageDesc) * p->n);
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tiles.size()));
@@ -343,6 +383,9 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   if (e == hipSuccess && !p->tiles.empty())
     e = hipMemcpy(p->d_tiles, p->tiles.data(), sizeof(ConvTile) * p->tiles.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), sizeof(int32_t) * p->n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_gtiles, sizeof(itc::GradTile) * p->gtiles.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_gtiles, p->gtiles.data(), sizeof(itc::GradTile) * p->gtiles.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     itc_lattice_plan_destroy(p);
     return device_fail(e, "plan upload");
@@ -353,11 +396,49 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
 
 int32_t itc_lattice_plan_size(const itc_plan* p) { return p ? p->n : -1; }
 
+itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps, const double* s_x, const void* w,
+                                                   const double* grad_d, void* grad_w, void* grad_weights,
+                                                   void* stream) {
+  if (!p || !maps || !w || !grad_d) return fail(ITC_E_NULL, "plan, maps, w and grad_d must be non-NULL");
+  if (grad_weights && !s_x) return fail(ITC_E_NULL, "s_x is required for grad_weights");
+  if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (grad_w) {
+    itc::FitArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.maps = maps;
+    a.w_init = w;
+    a.s_x_in = s_x;
+    a.theta = -1.0;
+    a.n = p->n;
+    a.m_max = p->m_max;
+    a.grad_w = grad_w;
+    a.grad_d = grad_d;
+    hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, s, nullptr);
+    if (e != hipSuccess) return device_fail(e, "batched codebook gradient launch");
+  }
+  if (grad_weights) {
+    itc::GradIArgs g;
+    std::memset(&g, 0, sizeof g);
+    g.maps = maps;
+    g.w = w;
+    g.s_x = s_x;
+    g.grad_d = grad_d;
+    g.grad_weights = grad_weights;
+    g.m_max = p->m_max;
+    hipError_t e = itc::launch_grad_weights(false, p->d_images, p->d_gtiles, (int)p->gtiles.size(), g,
+                                            p->grad_grid, s, nullptr);
+    if (e != hipSuccess) return device_fail(e, "batched weight gradient launch");
+  }
+  return ok();
+}
+
 void itc_lattice_plan_destroy(itc_plan* p) {
   if (!p) return;
   if (p->d_images) (void)hipFree(p->d_images);
   if (p->d_tiles) (void)hipFree(p->d_tiles);
   if (p->d_order) (void)hipFree(p->d_order);
+  if (p->d_gtiles) (void)hipFree(p->d_gtiles);
   delete p;
 }
 

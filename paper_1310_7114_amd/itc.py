@@ -62,6 +62,7 @@ SIGNATURES = {
     "itc_lattice_precompute_batched": (ctypes.c_int, [_P, _P, _P, _P]),
     "itc_lattice_fit_batched": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
+    "itc_lattice_divergence_backward_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_destroy": (None, [_P]),
     "itc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -211,34 +212,35 @@ class BatchPlan:
 
     images: sequence of (H, W) uint8/float tensors (host or device); ms: codevectors
     per image; sigmas, scales, iters: per image. The packed weights, maps and
-    codebook buffers are allocated once here.
+    codebook buffers are allocated once here. `BatchPlan.for_stack` describes a
+    contiguous (B, H, W) stack instead, whose weights are passed per call.
     """
 
-    def __init__(self, images: Sequence[torch.Tensor], ms: Sequence[int], sigmas: Sequence[float],
+    def __init__(self, images: Optional[Sequence[torch.Tensor]], ms: Sequence[int], sigmas: Sequence[float],
                  iters: Sequence[int], scales: Optional[Sequence[float]] = None,
-                 radii: Optional[Sequence[int]] = None, device="cuda"):
-        n = len(images)
+                 radii: Optional[Sequence[int]] = None, device="cuda", _shapes=None, _dtype=None):
+        shapes = [tuple(im.shape) for im in images] if images is not None else list(_shapes)
+        n = len(shapes)
         if n == 0:
             raise ValueError("empty batch")
         scales = [1.0] * n if scales is None else list(scales)
         radii = [0] * n if radii is None else list(radii)
-        dt = images[0].dtype
+        dt = images[0].dtype if images is not None else _dtype
         esz = torch.tensor([], dtype=dt).element_size()
         self.n = n
+        self.dtype = dt
+        self.shapes = shapes
         self.descs = (Desc * n)()
         wo, mo, wf, mlist, it = [], [], [], [], []
-        woff = moff = 0
-        foff = 0
-        for i, img in enumerate(images):
-            if img.dtype != dt:
+        woff = moff = foff = 0
+        for i, (H, W) in enumerate(shapes):
+            if images is not None and images[i].dtype != dt:
                 raise ValueError("all images of a batch share one storage dtype")
-            H, W = img.shape
-            d = make_desc(H, W, sigmas[i], dt, torch.float32, scales[i], radii[i])
-            self.descs[i] = d
+            self.descs[i] = make_desc(H, W, sigmas[i], dt, torch.float32, scales[i], radii[i])
             wo.append(woff)
-            woff += (H * W * esz + 255) // 256 * 256
+            woff += H * W * esz if images is None else (H * W * esz + 255) // 256 * 256
             mo.append(moff)
-            moff += maps_bytes(d)
+            moff += maps_bytes(self.descs[i])
             wf.append(foff)
             foff += int(ms[i])
             mlist.append(int(ms[i]))
@@ -251,16 +253,26 @@ class BatchPlan:
         self.w_offsets = wf
         self.ms = mlist
         self.total_w = foff
-        self.weights = torch.zeros(woff // esz, dtype=dt, device=device)
-        for i, img in enumerate(images):
-            H, W = img.shape
-            self.weights[wo[i] // esz: wo[i] // esz + H * W].copy_(img.reshape(-1).to(device))
-        self.maps = torch.empty(max(moff, 256), dtype=torch.uint8, device=device)
+        self.map_bytes_total = max(moff, 256)
         self.map_off_list = mo
+        self.weights = None
+        if images is not None:
+            self.weights = torch.zeros(woff // esz, dtype=dt, device=device)
+            for i, img in enumerate(images):
+                H, W = img.shape
+                self.weights[wo[i] // esz: wo[i] // esz + H * W].copy_(img.reshape(-1).to(device))
+        self.maps = torch.empty(self.map_bytes_total, dtype=torch.uint8, device=device)
         b = Batch(n, self.descs, self.weight_off, self.map_off, self.M, self.w_off_arr, self.iters)
         h = ctypes.c_void_p()
         _check(load().itc_lattice_plan_create(ctypes.byref(b), ctypes.byref(h)))
         self.handle = h
+
+    @classmethod
+    def for_stack(cls, B: int, H: int, W: int, M: int, sigma: float, iters: int = 0, dtype=torch.float32,
+                  scale: float = 1.0, radius: int = 0, device="cuda") -> "BatchPlan":
+        """Plan for a contiguous (B, H, W) weight stack and (B * M, 2) codebooks."""
+        return cls(None, [M] * B, [sigma] * B, [iters] * B, [scale] * B, [radius] * B, device=device,
+                   _shapes=[(H, W)] * B, _dtype=dtype)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -277,22 +289,41 @@ class BatchPlan:
     def unpack(self, flat: torch.Tensor, i: int) -> torch.Tensor:
         return flat[self.w_offsets[i]: self.w_offsets[i] + self.ms[i]]
 
-    def maps_of(self, i: int) -> Maps:
+    def new_maps(self) -> torch.Tensor:
+        return torch.empty(self.map_bytes_total, dtype=torch.uint8, device=self.maps.device)
+
+    def maps_of(self, i: int, maps: Optional[torch.Tensor] = None) -> Maps:
+        maps = self.maps if maps is None else maps
         d = self.descs[i]
         nb = maps_bytes(d)
-        buf = self.maps[self.map_off_list[i]: self.map_off_list[i] + nb]
-        return Maps(d, buf, torch.empty(1, dtype=torch.float64, device=self.maps.device), torch.float32)
+        buf = maps[self.map_off_list[i]: self.map_off_list[i] + nb]
+        return Maps(d, buf, torch.empty(1, dtype=torch.float64, device=maps.device), torch.float32)
 
-    def precompute(self):
-        _check(load().itc_lattice_precompute_batched(self.handle, _ptr(self.weights), _ptr(self.maps), _stream()))
+    def _w(self, weights):
+        w = self.weights if weights is None else weights
+        if w is None:
+            raise ValueError("this plan holds no weights: pass them")
+        return w
+
+    def precompute(self, weights=None, maps=None):
+        _check(load().itc_lattice_precompute_batched(self.handle, _ptr(self._w(weights)),
+                                                     _ptr(self.maps if maps is None else maps), _stream()))
 
     def fit(self, w_init: torch.Tensor, w_out: torch.Tensor, s_x=None, d_out=None, iters_done=None,
-            theta: float = -1.0):
-        _check(load().itc_lattice_fit_batched(self.handle, _ptr(self.maps), _ptr(w_init), float(theta),
-                                              _ptr(w_out), _ptr(s_x), _ptr(d_out), _ptr(iters_done), _stream()))
+            theta: float = -1.0, maps=None):
+        _check(load().itc_lattice_fit_batched(self.handle, _ptr(self.maps if maps is None else maps), _ptr(w_init),
+                                              float(theta), _ptr(w_out), _ptr(s_x), _ptr(d_out), _ptr(iters_done),
+                                              _stream()))
 
     def run(self, w_init: torch.Tensor, w_out: torch.Tensor, s_x=None, d_out=None, iters_done=None,
-            theta: float = -1.0):
-        _check(load().itc_lattice_run_batched(self.handle, _ptr(self.weights), _ptr(self.maps), _ptr(w_init),
+            theta: float = -1.0, weights=None, maps=None):
+        _check(load().itc_lattice_run_batched(self.handle, _ptr(self._w(weights)),
+                                              _ptr(self.maps if maps is None else maps), _ptr(w_init),
                                               float(theta), _ptr(w_out), _ptr(s_x), _ptr(d_out),
                                               _ptr(iters_done), _stream()))
+
+    def backward(self, w: torch.Tensor, s_x: torch.Tensor, grad_d: torch.Tensor, grad_w=None, grad_weights=None,
+                 maps=None):
+        _check(load().itc_lattice_divergence_backward_batched(
+            self.handle, _ptr(self.maps if maps is None else maps), _ptr(s_x), _ptr(w),
+            _ptr(grad_d.to(torch.float64).contiguous()), _ptr(grad_w), _ptr(grad_weights), _stream()))
