@@ -35,6 +35,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle leg")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-per-image", action="store_true")
+    p.add_argument("--copy-calib-mib", type=int, default=0,
+                   help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     return p.parse_args()
 
 
@@ -54,6 +56,14 @@ def main():
     itc.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.copy_calib_mib > 0:  # a plain copy kernel of known size, for counter calibration
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     t0 = time.time()
     cases = synth.config3_cases(args.images)
