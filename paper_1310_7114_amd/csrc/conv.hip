@@ -385,6 +385,7 @@ int conv_segment_rows(const ImageDesc& im) {
 }
 
 hipError_t launch_conv_image(bool f64, const ImageDesc& im, const void* w, void* m, hipStream_t s) {
+  if (conv_uses_mx(f64, im.wdtype)) return launch_conv_mx_image(im, w, m, s);
   const int S = conv_segment_rows(im);
   const dim3 grid(im.nstrips * ((im.H + S - 1) / S));
 #define ITC_CASE_F(RR)                                                                           \
@@ -407,6 +408,7 @@ hipError_t launch_conv_image(bool f64, const ImageDesc& im, const void* w, void*
 
 hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, const ConvTile* d_tiles,
                              int ntiles, const void* w, void* m, int grid, hipStream_t s) {
+  if (rclass >= CONV_MX_CLASS) return launch_conv_mx_tiles(rclass - CONV_MX_CLASS, d_images, d_tiles, ntiles, w, m, grid, s);
 #define ITC_CASE_F(RR)                                                                              \
   case RR:                                                                                         \
     hipLaunchKernelGGL((conv_tiles_kernel<float, RR>), dim3(grid), dim3(CONV_NT), 0, s, d_images,    \
@@ -426,6 +428,7 @@ hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, co
 }
 
 int conv_tiles_blocks_per_cu(bool f64, int rclass) {
+  if (rclass >= CONV_MX_CLASS) return conv_mx_blocks_per_cu(rclass - CONV_MX_CLASS);
   int nb = 0;
 #define ITC_CASE_F(RR)                                                                               \
   case RR:                                                                                          \

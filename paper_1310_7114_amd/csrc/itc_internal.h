@@ -70,6 +70,13 @@ struct ConvTile {
   int32_t S;
 };
 
+// Batched radius classes at or above CONV_MX_CLASS select the matrix-core
+// convolution (8-bit weights, FP32 maps) with aligned radius
+// class - CONV_MX_CLASS (a multiple of 8).
+constexpr int CONV_MX_CLASS = 64;
+inline bool conv_uses_mx(bool f64, int wdtype) { return !f64 && wdtype == 0; }
+int conv_mx_radius(int rclass);
+
 // Launchers (defined in the .hip files). All return hipError_t of the launch.
 // Single image (h_image by value, all strips and segments in one grid).
 hipError_t launch_conv_image(bool f64, const ImageDesc& h_image, const void* weights, void* maps,
@@ -82,6 +89,10 @@ int conv_tiles_blocks_per_cu(bool f64, int rclass);
 int fit_blocks_per_cu(bool f64, int m_max);
 // Segment rows used for a single image (multiple of CONV_CH).
 int conv_segment_rows(const ImageDesc& im);
+hipError_t launch_conv_mx_image(const ImageDesc& h_image, const void* weights, void* maps, hipStream_t s);
+hipError_t launch_conv_mx_tiles(int ra, const ImageDesc* d_images, const ConvTile* d_tiles, int ntiles,
+                                const void* weights, void* maps, int grid, hipStream_t s);
+int conv_mx_blocks_per_cu(int ra);
 hipError_t launch_sx_finalize(bool f64, const ImageDesc& img, const void* maps, double* s_x,
                               hipStream_t s);
 

@@ -298,8 +298,11 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   if (!p) return fail(ITC_E_DEVICE, "out of host memory");
   p->n = b->n;
   p->images.resize(b->n);
-  std::vector<std::vector<ConvTile>> by_class(64);
-  std::vector<std::vector<int64_t>> cost_of(64);
+  // class keys: the VALU kernel's radius class, or CONV_MX_CLASS + aligned
+  // radius for the matrix-core kernel (8-bit weights)
+  constexpr int NKEYS = itc::CONV_MX_CLASS + 33;
+  std::vector<std::vector<ConvTile>> by_class(NKEYS);
+  std::vector<std::vector<int64_t>> cost_of(NKEYS);
   std::vector<double> fit_cost(b->n);
   for (int i = 0; i < b->n; ++i) {
     int R = 0, rc = 0;
@@ -339,18 +342,19 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     int S = (im.H + nseg - 1) / nseg;
     S = (S + itc::CONV_CH - 1) / itc::CONV_CH * itc::CONV_CH;
     nseg = (im.H + S - 1) / S;
+    const int key = itc::conv_uses_mx(false, im.wdtype) ? itc::CONV_MX_CLASS + itc::conv_mx_radius(rc) : rc;
     for (int sg = 0; sg < nseg; ++sg) {
       const int rows = std::min(S, im.H - sg * S);
       for (int st2 = 0; st2 < im.nstrips; ++st2) {
-        by_class[rc].push_back(ConvTile{i, st2, sg * S, S});
-        cost_of[rc].push_back((int64_t)(rows + 2 * rc) * (2 * rc + 1));
+        by_class[key].push_back(ConvTile{i, st2, sg * S, S});
+        cost_of[key].push_back((int64_t)(rows + 2 * rc) * (2 * rc + 1));
       }
     }
     fit_cost[i] = (double)(im.iters + 1) * im.M * (im.M + 16.0);
     for (int u0 = 0; u0 < im.H; u0 += 64)
       for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
   }
-  for (int rc = 0; rc < 64; ++rc) {
+  for (int rc = 0; rc < NKEYS; ++rc) {
     if (by_class[rc].empty()) continue;
     std::vector<int> idx(by_class[rc].size());
     std::iota(idx.begin(), idx.end(), 0);
