@@ -32,6 +32,8 @@ def hipcc() -> str:
 def flags() -> list:
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core results in ordinary VGPRs (no accumulator-register copies)
+            "-mllvm", "-amdgpu-mfma-vgpr-form=1",
             f"-I{INCLUDE}", f"-I{CSRC}", "-Wno-unused-command-line-argument"]
 
 

@@ -37,6 +37,8 @@
 //      times the same tap fragments (as the A operand) -> A, M_u, M_v for 16
 //      rows x 16 columns, stored coalesced along rows, and h*A summed into
 //      the S_X partial of each 8-row group.
+#include <type_traits>
+
 #include "itc_device.h"
 
 namespace itc {
@@ -139,7 +141,8 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
       for (int e = 0; e < 8; ++e) {
         const int t = n + RA - (32 * s + 8 * q + e);
         const double gv = __shfl(gl, t < 0 ? -t : t);  // |t| <= 63; zero past the radius
-        const float gs = (float)(256.0 * gv), ts = (float)(256.0 * (double)t * gv);
+        float gs = (float)(256.0 * gv), ts = (float)(256.0 * (double)t * gv);
+        asm volatile("" : "+v"(gs), "+v"(ts));  // split the FP32 value (no fused f64 -> f16 rounding)
         const Split16 a = split16(gs), b = split16(ts);
         g_hi[s][e] = a.hi;
         g_lo[s][e] = a.lo;
@@ -161,28 +164,33 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
   }
   // Loads are unconditional (clamped offsets) and masked at staging time, a
   // chunk later, so that nothing waits on them in between.
-  uint32_t pre[4][G::CC];
-  uint32_t ymask = 0u;  // bit r: fetched row 4w + r lies inside the image (uniform)
-  auto fetch = [&](int j) {
-    ymask = 0u;
+  // Two chunks are in flight: set P = j & 1 holds chunk j from two chunks
+  // before it is staged (P is a template constant so the sets stay in
+  // registers), which leaves the loads two chunks of work to arrive.
+  uint32_t pre[2][4][G::CC];
+  uint32_t ymask[2] = {0u, 0u};  // bit r: fetched row 4w + r lies inside the image (uniform)
+  auto fetch = [&](int j, auto P) {
+    constexpr int p = decltype(P)::value;
+    ymask[p] = 0u;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int y = origin + j * MX_CH + 4 * wave + r;  // uniform
       const bool yin = y >= 0 && y < H;
-      ymask |= yin ? 1u << r : 0u;
+      ymask[p] |= yin ? 1u << r : 0u;
       const uint32_t soff = yin ? (uint32_t)y * rowbytes : 0u;
 #pragma unroll
-      for (int c = 0; c < G::CC; ++c) pre[r][c] = buf_load<uint8_t>(wres, xoff[c], soff);
+      for (int c = 0; c < G::CC; ++c) pre[p][r][c] = buf_load<uint8_t>(wres, xoff[c], soff);
     }
   };
-  auto stage_chunk = [&](int j) {
-    _Float16* xs = stage + (j & 1) * G::STAGE + (4 * wave) * G::SWP + lane;
+  auto stage_chunk = [&](int j, auto P) {
+    constexpr int p = decltype(P)::value;
+    _Float16* xs = stage + p * G::STAGE + (4 * wave) * G::SWP + lane;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const bool yin = (ymask >> r) & 1u;
+      const bool yin = (ymask[p] >> r) & 1u;
 #pragma unroll
       for (int c = 0; c < G::CC; ++c) {
-        const uint32_t v = yin && xok[c] ? pre[r][c] : 0u;
+        const uint32_t v = yin && xok[c] ? pre[p][r][c] : 0u;
         if (64 * c + 64 <= G::SW || lane + 64 * c < G::SW) xs[r * G::SWP + 64 * c] = (_Float16)(uint16_t)v;
       }
     }
@@ -190,6 +198,10 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
 
   const uint32_t mpb = (uint32_t)(im.map_pitch * sizeof(float));  // bytes per map row
   const uint32_t planeb = (uint32_t)H * mpb;
+  // one descriptor per plane: the three maps share a byte offset
+  const char* mimg = mbase + im.map_off;
+  const rsrc_t resA = make_rsrc(mimg, planeb), resU = make_rsrc(mimg + planeb, planeb),
+               resV = make_rsrc(mimg + 2 * (size_t)planeb, planeb);
   const int col = v0 + 16 * wave + n;  // this lane's output column (inside the padded pitch)
   const bool col_ok = col < W;
   const uint32_t part_base = (uint32_t)im.part_off + (uint32_t)((int64_t)strip * im.ngroups * CONV_TW * sizeof(float));
@@ -197,23 +209,23 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
   _Float16* ring_col = ring + (size_t)(16 * wave + n) * G::RINGP;
 
   // Map stores are unconditional: a row outside the segment gets a byte
-  // offset past the end of the buffer, which the hardware discards (the
-  // offset stays below 2^32 with every plane added: maps are < 2 GiB). With
-  // every chunk issuing the same memory operations, each wait on a load
-  // counts exactly the stores issued after it.
+  // offset past the end of its plane, which the hardware discards (the
+  // offset plus three rows stays below 2^32: maps are < 2 GiB). With every
+  // chunk issuing the same memory operations, each wait on a load counts
+  // exactly the stores issued after it.
   constexpr uint32_t MX_DISCARD = 0x80000000u;
   uint8_t* hcol = hring + (16 * wave + n) * G::RINGB;
 
   // One chunk: stage j, row pass j, column pass j - J0 (before the first
   // output chunk its results are discarded).
-  auto chunk = [&](int j) {
-    stage_chunk(j);
+  auto chunk = [&](int j, auto P) {
+    stage_chunk(j, P);
     __syncthreads();
-    fetch(j + 1);  // past the last chunk: rows outside the image, masked
+    fetch(j + 2, P);  // past the last chunk: rows outside the image, masked
 
     // ---------------- row pass: chunk j -> ring block j mod NB ----------------
     {
-      const _Float16* xs = stage + (j & 1) * G::STAGE + n * G::SWP + 16 * wave + 8 * q;
+      const _Float16* xs = stage + decltype(P)::value * G::STAGE + n * G::SWP + 16 * wave + 8 * q;
       f4_t r0 = {0.f, 0.f, 0.f, 0.f}, r1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < G::KS; ++s) {
@@ -224,7 +236,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         r1 = mfma(a, t_lo[s], r1);
       }
       // stored weights of rows 4q..4q+3 at this lane's column, for S_X
-      const _Float16* xh = stage + (j & 1) * G::STAGE + (4 * q) * G::SWP + RA + 16 * wave + n;
+      const _Float16* xh = stage + decltype(P)::value * G::STAGE + (4 * q) * G::SWP + RA + 16 * wave + n;
       uint32_t hb = 0u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) hb |= (uint32_t)(uint16_t)xh[i * G::SWP] << (8 * i);
@@ -253,54 +265,56 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     {
       const int jo = j - G::J0;
       const int o0 = s0 + jo * MX_CH;
-      f4_t ah = {0.f, 0.f, 0.f, 0.f}, al = ah, uh = ah, ul = ah, vh = ah, vl = ah;
+      f4_t am = {0.f, 0.f, 0.f, 0.f}, um = am, vm = am;
 #pragma unroll
       for (int s = 0; s < G::KS; ++s) {
         // window rows 32s + 8q .. +7 lie in ring block jo + 2s + q/2, half q&1
-        const int blk = (j + 1 + 2 * s + (q >> 1)) % G::NB;  // jo + NB = j + 1
+        // (jo + NB = j + 1 keeps the block index non-negative)
+        const int u0 = (j + 1 + 2 * s) % G::NB, u1 = (j + 2 + 2 * s) % G::NB;  // uniform
+        const int blk = (q >> 1) ? u1 : u0;
         const _Float16* rp = ring_col + blk * MX_CH + 8 * (q & 1);
         const h8_t y0h = *reinterpret_cast<const h8_t*>(rp);
         const h8_t y0l = *reinterpret_cast<const h8_t*>(rp + G::RINGA);
         const h8_t y1h = *reinterpret_cast<const h8_t*>(rp + 2 * G::RINGA);
         const h8_t y1l = *reinterpret_cast<const h8_t*>(rp + 3 * G::RINGA);
-        ah = mfma(g_hi[s], y0h, ah);
-        uh = mfma(t_hi[s], y0h, uh);
-        vh = mfma(g_hi[s], y1h, vh);
-        al = mfma(g_hi[s], y0l, al);
-        ul = mfma(t_hi[s], y0l, ul);
-        vl = mfma(g_hi[s], y1l, vl);
-        al = mfma(g_lo[s], y0h, al);
-        ul = mfma(t_lo[s], y0h, ul);
-        vl = mfma(g_lo[s], y1h, vl);
-        al = mfma(g_lo[s], y0l, al);
-        ul = mfma(t_lo[s], y0l, ul);
-        vl = mfma(g_lo[s], y1l, vl);
+        am = mfma(g_hi[s], y0h, am);
+        um = mfma(t_hi[s], y0h, um);
+        vm = mfma(g_hi[s], y1h, vm);
+        am = mfma(g_hi[s], y0l, am);
+        um = mfma(t_hi[s], y0l, um);
+        vm = mfma(g_hi[s], y1l, vm);
+        am = mfma(g_lo[s], y0h, am);
+        um = mfma(t_lo[s], y0h, um);
+        vm = mfma(g_lo[s], y1h, vm);
+        am = mfma(g_lo[s], y0l, am);
+        um = mfma(t_lo[s], y0l, um);
+        vm = mfma(g_lo[s], y1l, vm);
       }
       // stored weights of output rows o0 + 4q .. +3: window rows RA + 4q .. +3
-      const int hrow = 16 * (j + 1) + RA + 4 * q;  // (jo + NB) blocks, same residue
-      const uint32_t hb = *reinterpret_cast<const uint32_t*>(hcol + ((hrow / MX_CH) % G::NB) * MX_CH + hrow % MX_CH);
+      // (block jo + (RA + 4q)/16, offset (RA + 4q) mod 16)
+      const int hq = RA + 4 * q;
+      const int hb0 = (j + 1 + RA / MX_CH) % G::NB, hb1 = (j + 2 + RA / MX_CH) % G::NB;  // uniform
+      const int hblk = (RA % MX_CH + 4 * q) >= MX_CH ? hb1 : hb0;
+      const uint32_t hb = *reinterpret_cast<const uint32_t*>(hcol + hblk * MX_CH + hq % MX_CH);
+      // rows outside the segment (warm-up chunks, the tail of the last one)
+      // are discarded; interior chunks skip the per-row tests
+      const bool full = jo >= 0 && o0 + MX_CH <= seg_end;  // uniform
+      const uint32_t off0 = (uint32_t)(o0 + 4 * q) * mpb + (uint32_t)col * (uint32_t)sizeof(float);
       float sx = 0.f;
-      uint32_t off[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = o0 + 4 * q + i;
-        const bool ok = row >= s0 && row < seg_end;
-        const float a = (ah[i] + al[i]) * fac;
-        ah[i] = a;
-        uh[i] = (uh[i] + ul[i]) * fac;
-        vh[i] = (vh[i] + vl[i]) * fac;
-        const float h = (float)((hb >> (8 * i)) & 0xffu);
-        sx += ok && col_ok ? h * a : 0.f;
-        off[i] = ok ? (uint32_t)row * mpb + (uint32_t)col * (uint32_t)sizeof(float) : MX_DISCARD;
+        const bool ok = full || (row >= s0 && row < seg_end);
+        const uint32_t off = ok ? off0 + (uint32_t)i * mpb : MX_DISCARD;
+        const float a = am[i] * fac;
+        buf_store<float>(a, resA, off, 0u);
+        buf_store<float>(um[i] * fac, resU, off, 0u);
+        buf_store<float>(vm[i] * fac, resV, off, 0u);
+        const float h = ok ? (float)((hb >> (8 * i)) & 0xffu) : 0.f;  // zero past the width
+        sx = __builtin_fmaf(h, a, sx);
       }
       // rows 8p..8p+7 of the chunk are lanes q = 2p and 2p + 1
       sx += __shfl_xor(sx, 16);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        buf_store<float>(ah[i], mres, off[i], 0u);
-        buf_store<float>(uh[i], mres, off[i] + planeb, 0u);
-        buf_store<float>(vh[i], mres, off[i] + 2 * planeb, 0u);
-      }
       const int grow = o0 + 8 * (q >> 1);
       const uint32_t poff = (q & 1) == 0 && grow >= s0 && grow < seg_end
                                 ? part_base + (uint32_t)((grow / CONV_GROUP) * CONV_TW + 16 * wave + n) *
@@ -310,9 +324,17 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     }
   };
 
-  fetch(0);
-  chunk(0);  // peeled, so that the loop is entered with the same pending operations as it repeats
-  for (int j = 1; j < nchunks; ++j) chunk(j);
+  using P0 = std::integral_constant<int, 0>;
+  using P1 = std::integral_constant<int, 1>;
+  fetch(0, P0{});
+  fetch(1, P1{});
+  chunk(0, P0{});  // peeled, so that the loop is entered with the same pending operations as it repeats
+  int j = 1;
+  for (; j + 1 < nchunks; j += 2) {
+    chunk(j, P1{});
+    chunk(j + 1, P0{});
+  }
+  if (j < nchunks) chunk(j, P1{});
 }
 
 // Zero the rings once per workgroup: column passes of warm-up chunks read

@@ -23,7 +23,6 @@
 namespace itc {
 
 constexpr int FIT_NT = 256;
-constexpr int FIT_MAXPASS = ITC_MAX_CODEVECTORS_DEV / FIT_NT;
 constexpr double FIT_FAR = 1e30;
 
 using P2 = V2<double>;
@@ -33,20 +32,15 @@ __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ double exp2_neg(double x) { return exp2(-x); }
 
-// Lanes per codevector: minimise passes * ceil(M / P) with at most FIT_MAXPASS passes.
+// Lanes per codevector: the fewest passes the workgroup allows
+// (ceil(M / FIT_NT)), then the most lanes per codevector that still fit in
+// them. Many images run at once, so total work and registers (each pass
+// keeps its own state) matter more than one image's sequential steps.
 __host__ __device__ inline int lanes_per_codevector(int M) {
-  int bestP = 1, best = 1 << 30;
-  for (int P = 1; P <= 64; P <<= 1) {
-    const int slots = FIT_NT / P;
-    const int passes = (M + slots - 1) / slots;
-    if (passes > FIT_MAXPASS) continue;
-    const int cost = passes * ((M + P - 1) / P);
-    if (cost < best) {
-      best = cost;
-      bestP = P;
-    }
-  }
-  return bestP;
+  const int passes = (M + FIT_NT - 1) / FIT_NT;
+  int P = 1;
+  while (P < 64 && M * (2 * P) <= FIT_NT * passes) P <<= 1;
+  return P;
 }
 
 __host__ __device__ inline int padded_codebook(int M, int P) { return (M + 4 * P - 1) / (4 * P) * (4 * P); }
@@ -65,12 +59,17 @@ struct FitImageArgs {
   const double* grad_d;  // dL/dD (one double), gradient mode only
 };
 
-template <typename T, int P>
+template <typename T, int P, int MAXPASS>
 __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem) {
   constexpr int SLOTS = FIT_NT / P;
   const int M = im.M;
   const int Mpad = padded_codebook(M, P);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // lane-derived values are recomputed per image: an opaque thread index
+  // keeps the compiler from hoisting them out of the persistent image loop,
+  // where they would stay live in registers across it
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = tid >> 6;
   const int grp = tid / P, p = tid % P;
   const int npass = (M + SLOTS - 1) / SLOTS;
   P2* Wh = reinterpret_cast<P2*>(smem);                // scaled positions [Mpad]
@@ -81,9 +80,9 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   const V2<T>* w_in = reinterpret_cast<const V2<T>*>(a.w_init) + im.w_off;
 
   // owned codevectors (FP64, in registers; identical in all P lanes of a group)
-  double wu[FIT_MAXPASS], wv[FIT_MAXPASS];
+  double wu[MAXPASS], wv[MAXPASS];
 #pragma unroll
-  for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+  for (int ps = 0; ps < MAXPASS; ++ps) {
     const int k = ps * SLOTS + grp;
     wu[ps] = wv[ps] = 0.0;
     if (ps < npass && k < M) {
@@ -115,11 +114,11 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     const bool last = (t == im.iters) || stop;
     if (last && !need_d && !a.grad_w) break;
 
-    T Ak[FIT_MAXPASS], gu[FIT_MAXPASS], gv[FIT_MAXPASS], Eu[FIT_MAXPASS], Ev[FIT_MAXPASS];
-    T dAu[FIT_MAXPASS], dAv[FIT_MAXPASS];  // slope of the bilinear interpolant of A at w_k
+    T Ak[MAXPASS], gu[MAXPASS], gv[MAXPASS], Eu[MAXPASS], Ev[MAXPASS];
+    T dAu[MAXPASS], dAv[MAXPASS];  // slope of the bilinear interpolant of A at w_k
     double sxw = 0.0, sw = 0.0;
 #pragma unroll
-    for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+    for (int ps = 0; ps < MAXPASS; ++ps) {
       Ak[ps] = gu[ps] = gv[ps] = Eu[ps] = Ev[ps] = dAu[ps] = dAv[ps] = (T)0;
       if (ps < npass) {
         const int k = ps * SLOTS + grp;
@@ -220,7 +219,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       const T cb = (T)(2.0 * gd / (im.sigma * im.sigma * S_W) / s);  // E = E'/s
       V2<T>* gw = reinterpret_cast<V2<T>*>(a.grad_w) + im.w_off;
 #pragma unroll
-      for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+      for (int ps = 0; ps < MAXPASS; ++ps) {
         const int k = ps * SLOTS + grp;
         if (ps < npass && k < M && p == 0)
           gw[k] = V2<T>{fma_t(ca, dAu[ps], cb * Eu[ps]), fma_t(ca, dAv[ps], cb * Ev[ps])};
@@ -233,7 +232,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     const T cs = (T)(S_XW / S_W / s);  // c / s: E = E' / s
     float step = 0.0f;
 #pragma unroll
-    for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+    for (int ps = 0; ps < MAXPASS; ++ps) {
       if (ps < npass) {
         const int k = ps * SLOTS + grp;
         if (k < M && Ak[ps] != (T)0) {
@@ -263,7 +262,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   if (a.write_w) {
     V2<T>* w_o = reinterpret_cast<V2<T>*>(a.w_out) + im.w_off;
 #pragma unroll
-    for (int ps = 0; ps < FIT_MAXPASS; ++ps) {
+    for (int ps = 0; ps < MAXPASS; ++ps) {
       const int k = ps * SLOTS + grp;
       if (ps < npass && k < M && p == 0) w_o[k] = V2<T>{(T)wu[ps], (T)wv[ps]};
     }
@@ -272,20 +271,31 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   __syncthreads();  // shared memory is reused by the next image
 }
 
-template <typename T>
+// Passes over the owned codevectors an image needs: its codebook occupies
+// ceil(M P / FIT_NT) rounds of the workgroup's lanes.
+__host__ __device__ inline int fit_passes(int M) {
+  const int P = lanes_per_codevector(M);
+  return (M * P + FIT_NT - 1) / FIT_NT;
+}
+
+// Kernels are compiled for a bound on the passes (1, 2 or 4) so that the
+// per-pass registers of codebooks up to 256 codevectors cost nothing for the
+// larger ones; the lanes per codevector depend on M alone, so an image gets
+// the same arithmetic from every variant.
+template <typename T, int MAXPASS>
 __device__ __forceinline__ void fit_dispatch(const ImageDesc& im, const FitImageArgs& a, char* smem) {
   switch (lanes_per_codevector(im.M)) {
-    case 1: fit_image<T, 1>(im, a, smem); break;
-    case 2: fit_image<T, 2>(im, a, smem); break;
-    case 4: fit_image<T, 4>(im, a, smem); break;
-    case 8: fit_image<T, 8>(im, a, smem); break;
-    case 16: fit_image<T, 16>(im, a, smem); break;
-    case 32: fit_image<T, 32>(im, a, smem); break;
-    default: fit_image<T, 64>(im, a, smem); break;
+    case 1: fit_image<T, 1, MAXPASS>(im, a, smem); break;
+    case 2: fit_image<T, 2, MAXPASS>(im, a, smem); break;
+    case 4: fit_image<T, 4, MAXPASS>(im, a, smem); break;
+    case 8: fit_image<T, 8, MAXPASS>(im, a, smem); break;
+    case 16: fit_image<T, 16, MAXPASS>(im, a, smem); break;
+    case 32: fit_image<T, 32, MAXPASS>(im, a, smem); break;
+    default: fit_image<T, 64, MAXPASS>(im, a, smem); break;
   }
 }
 
-template <typename T>
+template <typename T, int MAXPASS>
 __global__ void __launch_bounds__(FIT_NT) fit_image_kernel(ImageDesc im, FitArgs fa) {
   extern __shared__ __align__(16) char smem[];
   FitImageArgs a;
@@ -300,10 +310,10 @@ __global__ void __launch_bounds__(FIT_NT) fit_image_kernel(ImageDesc im, FitArgs
   a.write_w = fa.write_w != 0;
   a.grad_w = fa.grad_w;
   a.grad_d = fa.grad_d;
-  fit_dispatch<T>(im, a, smem);
+  fit_dispatch<T, MAXPASS>(im, a, smem);
 }
 
-template <typename T>
+template <typename T, int MAXPASS>
 __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __restrict__ images,
                                                              const int32_t* __restrict__ order, FitArgs fa) {
   extern __shared__ __align__(16) char smem[];
@@ -326,7 +336,7 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
     a.write_w = fa.write_w != 0;
     a.grad_w = fa.grad_w;
     a.grad_d = fa.grad_d ? fa.grad_d + i : nullptr;
-    fit_dispatch<T>(im, a, smem);
+    fit_dispatch<T, MAXPASS>(im, a, smem);
   }
 }
 
@@ -338,30 +348,54 @@ static size_t fit_smem(int m_max) {
   return (size_t)mp * sizeof(P2) + 12 * sizeof(double) + 64;
 }
 
-int fit_blocks_per_cu(bool f64, int m_max) {
+int fit_passes_of(int M) { return fit_passes(M); }
+
+static int maxpass_bound(int np) { return np <= 1 ? 1 : (np <= 2 ? 2 : 4); }
+static int maxpass_for(int m_max) { return maxpass_bound(fit_passes(m_max)); }
+
+template <typename T, int MP>
+static int fit_occupancy(int m_max) {
   int nb = 0;
-  hipError_t e = f64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_batched_kernel<double>, FIT_NT,
-                                                                    fit_smem(m_max))
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_batched_kernel<float>, FIT_NT,
-                                                                    fit_smem(m_max));
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_batched_kernel<T, MP>, FIT_NT, fit_smem(m_max));
   return e == hipSuccess ? nb : 0;
+}
+
+int fit_blocks_per_cu(bool f64, int m_max, int max_passes) {
+  switch (maxpass_bound(max_passes)) {
+    case 1: return f64 ? fit_occupancy<double, 1>(m_max) : fit_occupancy<float, 1>(m_max);
+    case 2: return f64 ? fit_occupancy<double, 2>(m_max) : fit_occupancy<float, 2>(m_max);
+    default: return f64 ? fit_occupancy<double, 4>(m_max) : fit_occupancy<float, 4>(m_max);
+  }
+}
+
+template <typename T, int MP>
+static void launch_fit_t(const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a, int grid,
+                         hipStream_t s, const ImageDesc* h_image) {
+  if (h_image)
+    hipLaunchKernelGGL((fit_image_kernel<T, MP>), dim3(1), dim3(FIT_NT), fit_smem(h_image->M), s, *h_image, a);
+  else
+    hipLaunchKernelGGL((fit_batched_kernel<T, MP>), dim3(grid), dim3(FIT_NT), fit_smem(a.m_max), s, d_images,
+                       d_order, a);
 }
 
 hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
                       int grid, hipStream_t s, const ImageDesc* h_image) {
-  if (h_image) {
-    if (f64)
-      hipLaunchKernelGGL(fit_image_kernel<double>, dim3(1), dim3(FIT_NT), fit_smem(h_image->M), s, *h_image, a);
-    else
-      hipLaunchKernelGGL(fit_image_kernel<float>, dim3(1), dim3(FIT_NT), fit_smem(h_image->M), s, *h_image, a);
-    return hipGetLastError();
+  // passes are bounded by the largest codebook of the launch (in the
+  // gradient-only mode as well, which runs the same per-image code)
+  switch (h_image ? maxpass_for(h_image->M) : (a.max_passes > 0 ? maxpass_bound(a.max_passes) : 4)) {
+    case 1:
+      f64 ? launch_fit_t<double, 1>(d_images, d_order, a, grid, s, h_image)
+          : launch_fit_t<float, 1>(d_images, d_order, a, grid, s, h_image);
+      break;
+    case 2:
+      f64 ? launch_fit_t<double, 2>(d_images, d_order, a, grid, s, h_image)
+          : launch_fit_t<float, 2>(d_images, d_order, a, grid, s, h_image);
+      break;
+    default:
+      f64 ? launch_fit_t<double, 4>(d_images, d_order, a, grid, s, h_image)
+          : launch_fit_t<float, 4>(d_images, d_order, a, grid, s, h_image);
+      break;
   }
-  if (f64)
-    hipLaunchKernelGGL(fit_batched_kernel<double>, dim3(grid), dim3(FIT_NT), fit_smem(a.m_max), s, d_images,
-                       d_order, a);
-  else
-    hipLaunchKernelGGL(fit_batched_kernel<float>, dim3(grid), dim3(FIT_NT), fit_smem(a.m_max), s, d_images,
-                       d_order, a);
   return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, co
                              int ntiles, const void* weights, void* maps, int grid, hipStream_t s);
 // Resident workgroups per compute unit of the persistent kernels (0 on error).
 int conv_tiles_blocks_per_cu(bool f64, int rclass);
-int fit_blocks_per_cu(bool f64, int m_max);
+int fit_blocks_per_cu(bool f64, int m_max, int max_passes);
 // Segment rows used for a single image (multiple of CONV_CH).
 int conv_segment_rows(const ImageDesc& im);
 hipError_t launch_conv_mx_image(const ImageDesc& h_image, const void* weights, void* maps, hipStream_t s);
@@ -111,7 +111,11 @@ struct FitArgs {
   int32_t write_w;       // 0: do not write w_out (divergence only)
   void* grad_w;          // non-null: gradient mode, dL/dw at w_init (same layout), no update
   const double* grad_d;  // gradient mode: dL/dD per image
+  int32_t max_passes;    // largest fit_passes(M) of the launch (0: derive from m_max)
 };
+
+// Passes of the fit over an image's owned codevectors (1..4).
+int fit_passes_of(int M);
 
 hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
                       int grid, hipStream_t s, const ImageDesc* h_image);

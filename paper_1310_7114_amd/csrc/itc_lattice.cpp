@@ -131,6 +131,7 @@ int device_cus() {
 struct itc_plan {
   int n = 0;
   int m_max = 0;
+  int max_passes = 1;  // largest fit pass count over the images
   std::vector<ImageDesc> images;
   // tile list grouped by radius class: [begin, end) per class
   std::vector<ConvTile> tiles;
@@ -337,6 +338,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     im.iters = b->iters[i];
     p->images[i] = im;
     p->m_max = std::max(p->m_max, im.M);
+    p->max_passes = std::max(p->max_passes, itc::fit_passes_of(im.M));
     // tiles: segments of at most ~256 rows, multiples of the chunk height
     int nseg = (im.H + 255) / 256;
     int S = (im.H + nseg - 1) / nseg;
@@ -374,7 +376,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     if (per < 1) per = 1;
     p->cls_grid.push_back(std::min(p->cls_end[c] - p->cls_begin[c], per * cus));
   }
-  int fper = itc::fit_blocks_per_cu(false, p->m_max);
+  int fper = itc::fit_blocks_per_cu(false, p->m_max, p->max_passes);
   if (fper < 1) fper = 1;
   p->fit_grid = std::min(p->n, fper * cus);
   p->grad_grid = std::min((int)p->gtiles.size(), 4 * cus);
@@ -416,6 +418,7 @@ itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps
     a.theta = -1.0;
     a.n = p->n;
     a.m_max = p->m_max;
+    a.max_passes = p->max_passes;
     a.grad_w = grad_w;
     a.grad_d = grad_d;
     hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, s, nullptr);
@@ -474,6 +477,7 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
   a.theta = theta;
   a.n = p->n;
   a.m_max = p->m_max;
+  a.max_passes = p->max_passes;
   a.write_w = 1;
   hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, (hipStream_t)stream, nullptr);
   if (e != hipSuccess) return device_fail(e, "batched fit launch");
