@@ -154,16 +154,16 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
   }
 
   // ---- staging: wave w loads rows 4w..4w+3 of a chunk, staged columns lane + 64c ----
+  // Lanes past the staged width or outside the image load at an offset past
+  // the end of the buffer: the hardware returns 0 without a memory request.
   uint32_t xoff[G::CC];
-  bool xok[G::CC];
 #pragma unroll
   for (int c = 0; c < G::CC; ++c) {
     const int sc = lane + 64 * c, x = v0 - RA + sc;
-    xok[c] = sc < G::SW && x >= 0 && x < W;
-    xoff[c] = xok[c] ? (uint32_t)x : 0u;
+    xoff[c] = sc < G::SW && x >= 0 && x < W ? (uint32_t)x : 0x80000000u;
   }
-  // Loads are unconditional (clamped offsets) and masked at staging time, a
-  // chunk later, so that nothing waits on them in between.
+  // Loads are unconditional and rows outside the image are masked at staging
+  // time, a chunk later, so that nothing waits on them in between.
   // Two chunks are in flight: set P = j & 1 holds chunk j from two chunks
   // before it is staged (P is a template constant so the sets stay in
   // registers), which leaves the loads two chunks of work to arrive.
@@ -190,7 +190,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
       const bool yin = (ymask[p] >> r) & 1u;
 #pragma unroll
       for (int c = 0; c < G::CC; ++c) {
-        const uint32_t v = yin && xok[c] ? pre[p][r][c] : 0u;
+        const uint32_t v = yin ? pre[p][r][c] : 0u;
         if (64 * c + 64 <= G::SW || lane + 64 * c < G::SW) xs[r * G::SWP + 64 * c] = (_Float16)(uint16_t)v;
       }
     }

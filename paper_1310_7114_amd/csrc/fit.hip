@@ -17,7 +17,8 @@
 // exp2(-|w_j' - w_k'|^2) and its repulsion sum is E = E'/s. Pair differences
 // are formed in FP64 and rounded once to the map type, in which the
 // Gaussians and sums are evaluated. The LDS codebook is padded to a multiple
-// of 4P with points at 1e30, whose Gaussian is exactly 0.
+// of 4P, plus one group of 4P that the pair loop reads ahead, with points at
+// 1e30, whose Gaussian is exactly 0.
 #include "itc_device.h"
 
 namespace itc {
@@ -73,7 +74,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   const int grp = tid / P, p = tid % P;
   const int npass = (M + SLOTS - 1) / SLOTS;
   P2* Wh = reinterpret_cast<P2*>(smem);                // scaled positions [Mpad]
-  double* red = reinterpret_cast<double*>(Wh + Mpad);  // [4 waves][2]
+  double* red = reinterpret_cast<double*>(Wh + Mpad + 4 * P);  // [4 waves][2]
   double* red2 = red + 8;                              // [4 waves]
 
   const double s = sqrt(1.4426950408889634 / (2.0 * im.sigma * im.sigma));
@@ -91,7 +92,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       wv[ps] = (double)w.v;
     }
   }
-  for (int k = tid; k < Mpad; k += FIT_NT) {
+  for (int k = tid; k < Mpad + 4 * P; k += FIT_NT) {  // one padded group past Mpad: read ahead
     P2 h{FIT_FAR, FIT_FAR};
     if (k < M) {
       const V2<T> w = w_in[k];
@@ -155,17 +156,37 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
         T C = 0, Cu = 0, Cv = 0;
         if (own) {
           const double hu = s * uk, hv = s * vk;
+          // the next group of four is read while this one is evaluated, and
+          // even and odd pairs accumulate separately: two independent chains
+          T C1 = 0, Cu1 = 0, Cv1 = 0;
+          P2 nx[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) nx[u] = wcol[u * P];
           for (int jt = 0; jt < Mpad; jt += 4 * P) {
+            P2 cur[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const P2 wj = wcol[jt + u * P];
-              const T du = (T)(wj.u - hu), dv = (T)(wj.v - hv);
+              cur[u] = nx[u];
+              nx[u] = wcol[jt + 4 * P + u * P];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const T du = (T)(cur[u].u - hu), dv = (T)(cur[u].v - hv);
               const T e = exp2_neg(fma_t(du, du, dv * dv));
-              C += e;
-              Cu = fma_t(e, du, Cu);
-              Cv = fma_t(e, dv, Cv);
+              if (u & 1) {
+                C1 += e;
+                Cu1 = fma_t(e, du, Cu1);
+                Cv1 = fma_t(e, dv, Cv1);
+              } else {
+                C += e;
+                Cu = fma_t(e, du, Cu);
+                Cv = fma_t(e, dv, Cv);
+              }
             }
           }
+          C += C1;
+          Cu += Cu1;
+          Cv += Cv1;
         }
         C = group_sum<P>(C);
         Cu = group_sum<P>(Cu);
@@ -344,7 +365,10 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
 // codebook (largest over every P) plus the reduction scratch.
 static size_t fit_smem(int m_max) {
   int mp = 0;
-  for (int P = 1; P <= 64; P <<= 1) mp = mp > padded_codebook(m_max, P) ? mp : padded_codebook(m_max, P);
+  for (int P = 1; P <= 64; P <<= 1) {
+    const int need = padded_codebook(m_max, P) + 4 * P;  // plus the read-ahead group
+    mp = mp > need ? mp : need;
+  }
   return (size_t)mp * sizeof(P2) + 12 * sizeof(double) + 64;
 }
 
