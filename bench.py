@@ -1,5 +1,5 @@
 """Benchmark: images/s to the converged codebook, batched vs per-image, with the
-convolution's roofline and the FP64 oracle timed beside it.
+fit's and the convolution's rooflines and the FP64 oracle timed beside it.
 
 Default workload: the batch of 1,400 star silhouettes (W 128..1024 x H 128..768,
 binary uint8, M in 10..200, sigma in {2, 4, 8}, 100 sweeps, FP32), inputs
@@ -11,6 +11,7 @@ Prints one JSON line (rank 0). Runs on one GPU only.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +25,33 @@ METRIC = "images/sec to converged codebook (batched vs per-image); conv HBM GB/s
 HBM_PEAK_GBS = 8000.0
 # FP32 FMA without packed instructions: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 VALU_PEAK_TFLOPS = 78.6
+# one ordered codebook pair of a sweep: 2 differences, |d|^2 (mul + fma), exp2,
+# C += e, Cu += e du, Cv += e dv
+FIT_FLOPS_PER_PAIR = 11.0
+
+
+def profile_figures(group: str):
+    """Key/value figures of a committed rocprofv3 summary (profiles/<group>.md), or None when the
+    kernel sources no longer hash to the value recorded with the counters."""
+    path = os.path.join(ROOT, "profiles", f"{group}.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k] = v
+    try:
+        h = hashlib.sha256()
+        for f in kv["source_files"].split():
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        return {k: float(kv[k]) for k in ("traffic_bytes_per_step", "average_us_per_step")}
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def parse():
@@ -35,6 +63,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle leg")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-per-image", action="store_true")
+    p.add_argument("--eager", action="store_true",
+                   help="launch on the stream instead of replaying a HIP graph (for counter profiling)")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     return p.parse_args()
@@ -86,16 +116,20 @@ def main():
             plan.run(w0, w, sx, dd, done)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        plan.run(w0, w, sx, dd, done)
+    if args.eager:
+        step = lambda: plan.run(w0, w, sx, dd, done)  # noqa: E731
+    else:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run(w0, w, sx, dd, done)
+        step = graph.replay
     for _ in range(args.warmup):
-        graph.replay()
+        step()
     torch.cuda.synchronize()
-    print("[bench] warm-up done; timing batched graph replays", file=sys.stderr, flush=True)
+    print("[bench] warm-up done; timing batched steps", file=sys.stderr, flush=True)
     t = time.perf_counter()
     for _ in range(args.steps):
-        graph.replay()
+        step()
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t) / args.steps
     assert bool(torch.all(done == 100)) and bool(torch.all(torch.isfinite(dd)))
@@ -117,11 +151,17 @@ def main():
     fit_s = float(np.mean(fit_ms)) / 1e3
 
     # algorithmic work of the convolution: 1 B in + 3 x 4 B out per pixel;
-    # 5 filters x (2R+1) taps FMA per pixel (2 flop each)
+    # 5 filters x (2R+1) taps FMA per pixel (2 flop each) in the direct form
     conv_bytes = 13.0 * npx
     conv_flops = float(sum(2.0 * 5 * (2 * c.R + 1) * c.img.size for c in cases))
     conv_gbs = conv_bytes / conv_s / 1e9
     conv_tfs = conv_flops / conv_s / 1e12
+    # algorithmic work of the fit (the dominant single kernel): every sweep,
+    # and the final divergence, evaluates all M^2 ordered codebook pairs
+    fit_flops = FIT_FLOPS_PER_PAIR * float(sum((c.iters + 1) * c.M * c.M for c in cases))
+    fit_tfs = fit_flops / fit_s / 1e12
+    fit_prof = profile_figures("fit_silhouettes1400")
+    conv_prof = profile_figures("conv_silhouettes1400")
 
     # ---------------- per-image loop (same kernels, one image at a time) ----------------
     per_image = None
@@ -194,16 +234,22 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"silhouettes-{n}: binary star polygons, W 128..1024 x H 128..768, "
-                               f"M 10..200, sigma 2/4/8, 100 sweeps, batched persistent + HIP graph",
+                               f"M 10..200, sigma 2/4/8, 100 sweeps, batched persistent + "
+                               + ("stream launches" if args.eager else "HIP graph"),
                    "images": n, "pixels": npx, "iters": 100},
         "phases_ms": {"conv": conv_s * 1e3, "fit_and_divergence": fit_s * 1e3},
         "per_image": per_image,
         "batched_over_per_image": (value / per_image["value"]) if per_image else None,
-        "conv_hbm": {"achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": conv_gbs / HBM_PEAK_GBS, "bytes_per_px": 13},
-        "roofline": {"bound": "alu", "achieved": conv_tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": conv_tfs / VALU_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "convolution maps (per-radius-class persistent launches)"},
+        "roofline": {"bound": "alu", "achieved": fit_tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fit_tfs / VALU_PEAK_TFLOPS,
+                     "traffic": fit_prof["traffic_bytes_per_step"] if fit_prof else None,
+                     "kernel": "fit_batched_kernel (all sweeps + D, one launch)",
+                     "flops_per_pair": FIT_FLOPS_PER_PAIR},
+        "conv_hbm": {"bound": "hbm", "achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": conv_gbs / HBM_PEAK_GBS, "bytes_per_px": 13,
+                     "traffic": conv_prof["traffic_bytes_per_step"] if conv_prof else None,
+                     "direct_form_tflops": conv_tfs,
+                     "kernel": "conv_mx_tiles_kernel (one launch per aligned radius)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
