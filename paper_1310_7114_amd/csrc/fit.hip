@@ -25,6 +25,9 @@ namespace itc {
 
 constexpr int FIT_NT = 256;
 constexpr double FIT_FAR = 1e30;
+// A byte offset past the end of any maps buffer (< 2 GiB with every plane
+// added): buffer loads there return 0 without touching memory.
+constexpr uint32_t FIT_OOB = 0x80000000u;
 
 using P2 = V2<double>;
 
@@ -107,6 +110,15 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   const uint32_t planeb = (uint32_t)H * (uint32_t)mpl * (uint32_t)sizeof(T);
   const rsrc_t mres = make_rsrc(a.mbase + im.map_off, 3u * planeb);
   const bool need_d = a.d_trace != nullptr || a.d_out != nullptr;
+  // corner values of the cell each owned codevector was last read in (key -2: none yet)
+  int cell[MAXPASS];
+  T cav[MAXPASS][4], cmu[MAXPASS][4], cmv[MAXPASS][4];
+#pragma unroll
+  for (int ps = 0; ps < MAXPASS; ++ps) {
+    cell[ps] = -2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cav[ps][c] = cmu[ps][c] = cmv[ps][c] = (T)0;
+  }
   const P2* wcol = Wh + p;  // this lane's column of the pair loop: j = p + P t
 
   bool stop = false;
@@ -125,33 +137,39 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
         const int k = ps * SLOTS + grp;
         const bool own = k < M;
         const double uk = wu[ps], vk = wv[ps];
-        // ---- data terms: bilinear read of A, M_u, M_v at w_k. The 12 loads are
-        // issued here and consumed after the pair loop, which hides their latency.
-        // Off-lattice corners load a clamped in-bounds element and are zeroed.
+        // ---- data terms: bilinear read of A, M_u, M_v at w_k. The 12 corner
+        // values of the lattice cell holding w_k stay in registers until w_k
+        // enters another cell (near convergence it rarely does), so the maps
+        // are read again only then. The loads are issued here and consumed
+        // after the pair loop, which hides their latency. Off-lattice corners
+        // load at an offset past the end of the maps, which reads 0.
         T fu = 0, fv = 0;
-        T av[4], mu[4], mv[4];
         {
           const bool inside = own && uk > -1.0 && uk < (double)H && vk > -1.0 && vk < (double)W;
           const double fu0 = inside ? floor(uk) : 0.0, fv0 = inside ? floor(vk) : 0.0;
           const int i0 = (int)fu0, j0 = (int)fv0;
           fu = (T)(uk - fu0);
           fv = (T)(vk - fv0);
-          const bool r0 = inside && i0 >= 0, r1 = inside && i0 + 1 < H;
-          const bool c0 = j0 >= 0, c1 = j0 + 1 < W;
-          const uint32_t base = (uint32_t)(i0 * mpl + j0) * (uint32_t)sizeof(T);
+          const int key = inside ? (i0 + 1) * (W + 2) + (j0 + 1) : -1;
+          if (key != cell[ps]) {
+            cell[ps] = key;
+            const bool r0 = inside && i0 >= 0, r1 = inside && i0 + 1 < H;
+            const bool c0 = j0 >= 0, c1 = j0 + 1 < W;
+            const uint32_t base = (uint32_t)(i0 * mpl + j0) * (uint32_t)sizeof(T);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int di = c >> 1, dj = c & 1;
-            const bool ok = (di ? r1 : r0) && (dj ? c1 : c0);
-            const uint32_t off = ok ? base + (uint32_t)(di * mpl + dj) * (uint32_t)sizeof(T) : 0u;
-            const T x0 = buf_load<T>(mres, off, 0);
-            const T x1 = buf_load<T>(mres, off, planeb);
-            const T x2 = buf_load<T>(mres, off, 2 * planeb);
-            av[c] = ok ? x0 : (T)0;
-            mu[c] = ok ? x1 : (T)0;
-            mv[c] = ok ? x2 : (T)0;
+            for (int c = 0; c < 4; ++c) {
+              const int di = c >> 1, dj = c & 1;
+              const bool ok = (di ? r1 : r0) && (dj ? c1 : c0);
+              const uint32_t off = ok ? base + (uint32_t)(di * mpl + dj) * (uint32_t)sizeof(T) : FIT_OOB;
+              cav[ps][c] = buf_load<T>(mres, off, 0);
+              cmu[ps][c] = buf_load<T>(mres, off, planeb);
+              cmv[ps][c] = buf_load<T>(mres, off, 2 * planeb);
+            }
           }
         }
+        const T* av = cav[ps];
+        const T* mu = cmu[ps];
+        const T* mv = cmv[ps];
         // ---- codebook terms over j = p, p + P, ... (scaled coordinates) ----
         T C = 0, Cu = 0, Cv = 0;
         if (own) {
