@@ -11,13 +11,16 @@
 // batched launch.
 //
 // Precision: codevector positions are FP64 whatever the map type (with FP32
-// coordinates the rounding of w, 2.4e-4 px near u = 2048, would dominate the
-// error). Owners keep their positions in registers; LDS holds a copy scaled
-// by s = sqrt(log2(e) / (2 sigma^2)), so that a pair's Gaussian is
+// coordinates the rounding of w, 2.4e-4 px near u = 2048, accumulated over
+// the sweeps, would dominate the error). Owners keep their positions in
+// registers; LDS holds a copy in the map type, relative to the image centre
+// and scaled by s = sqrt(log2(e) / (2 sigma^2)), so that a pair's Gaussian is
 // exp2(-|w_j' - w_k'|^2) and its repulsion sum is E = E'/s. Pair differences
-// are formed in FP64 and rounded once to the map type, in which the
-// Gaussians and sums are evaluated. The LDS codebook is padded to a multiple
-// of 4P, plus one group of 4P that the pair loop reads ahead, with points at
+// are one subtraction in the map type: in FP32 the rounding of the centred,
+// scaled copies (at most half an ulp of s max(H, W) / 2) perturbs a near
+// pair's Gaussian by a few 1e-5 relative, far below the data term's effect;
+// FP64 keeps FP64 differences. The LDS codebook is padded to a multiple of
+// 4P, plus one group of 4P that the pair loop reads ahead, with points at
 // 1e30, whose Gaussian is exactly 0.
 #include "itc_device.h"
 
@@ -76,11 +79,14 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   const int lane = tid & 63, wave = tid >> 6;
   const int grp = tid / P, p = tid % P;
   const int npass = (M + SLOTS - 1) / SLOTS;
-  P2* Wh = reinterpret_cast<P2*>(smem);                // scaled positions [Mpad]
-  double* red = reinterpret_cast<double*>(Wh + Mpad + 4 * P);  // [4 waves][2]
-  double* red2 = red + 8;                              // [4 waves]
+  using Q2 = V2<T>;
+  Q2* Wh = reinterpret_cast<Q2*>(smem);  // centred scaled positions [Mpad + 4P]
+  double* red = reinterpret_cast<double*>(smem + (size_t)(Mpad + 4 * P) * sizeof(P2));  // [4 waves][2]
+  double* red2 = red + 8;                                                         // [4 waves]
 
   const double s = sqrt(1.4426950408889634 / (2.0 * im.sigma * im.sigma));
+  const double cu = 0.5 * im.H, cv = 0.5 * im.W;  // reference point of the LDS copy
+  auto lds_pos = [&](double u, double v) { return Q2{(T)(s * (u - cu)), (T)(s * (v - cv))}; };
   const V2<T>* w_in = reinterpret_cast<const V2<T>*>(a.w_init) + im.w_off;
 
   // owned codevectors (FP64, in registers; identical in all P lanes of a group)
@@ -96,10 +102,10 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     }
   }
   for (int k = tid; k < Mpad + 4 * P; k += FIT_NT) {  // one padded group past Mpad: read ahead
-    P2 h{FIT_FAR, FIT_FAR};
+    Q2 h{(T)FIT_FAR, (T)FIT_FAR};
     if (k < M) {
       const V2<T> w = w_in[k];
-      h = P2{s * (double)w.u, s * (double)w.v};
+      h = lds_pos((double)w.u, (double)w.v);
     }
     Wh[k] = h;
   }
@@ -119,7 +125,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
 #pragma unroll
     for (int c = 0; c < 4; ++c) cav[ps][c] = cmu[ps][c] = cmv[ps][c] = (T)0;
   }
-  const P2* wcol = Wh + p;  // this lane's column of the pair loop: j = p + P t
+  const Q2* wcol = Wh + p;  // this lane's column of the pair loop: j = p + P t
 
   bool stop = false;
   int t = 0;
@@ -173,15 +179,16 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
         // ---- codebook terms over j = p, p + P, ... (scaled coordinates) ----
         T C = 0, Cu = 0, Cv = 0;
         if (own) {
-          const double hu = s * uk, hv = s * vk;
+          const Q2 hk = lds_pos(uk, vk);
+          const T hu = hk.u, hv = hk.v;
           // the next group of four is read while this one is evaluated, and
           // even and odd pairs accumulate separately: two independent chains
           T C1 = 0, Cu1 = 0, Cv1 = 0;
-          P2 nx[4];
+          Q2 nx[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) nx[u] = wcol[u * P];
           for (int jt = 0; jt < Mpad; jt += 4 * P) {
-            P2 cur[4];
+            Q2 cur[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               cur[u] = nx[u];
@@ -189,7 +196,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const T du = (T)(cur[u].u - hu), dv = (T)(cur[u].v - hv);
+              const T du = cur[u].u - hu, dv = cur[u].v - hv;
               const T e = exp2_neg(fma_t(du, du, dv * dv));
               if (u & 1) {
                 C1 += e;
@@ -268,7 +275,12 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     if (last) break;
 
     // ---- Jacobi update of every owned codevector (all P lanes alike) ----
-    const T cs = (T)(S_XW / S_W / s);  // c / s: E = E' / s
+    // c / s (E = E' / s), in the map type
+    T cs;
+    if constexpr (sizeof(T) == 4)
+      cs = (T)S_XW * recip((T)S_W * (T)s);
+    else
+      cs = (T)(S_XW / S_W / s);
     float step = 0.0f;
 #pragma unroll
     for (int ps = 0; ps < MAXPASS; ++ps) {
@@ -281,7 +293,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
           wu[ps] += (double)du;
           wv[ps] += (double)dv;
           if (a.theta >= 0.0) step = fmaxf(step, (float)sqrt((double)du * du + (double)dv * dv));
-          if (p == 0) Wh[k] = P2{s * wu[ps], s * wv[ps]};
+          if (p == 0) Wh[k] = lds_pos(wu[ps], wv[ps]);
         }
       }
     }
