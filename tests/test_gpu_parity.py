@@ -47,6 +47,12 @@ MAP_CASES = [
     ("class_pad_r8", lambda: S.config1_case(3).img, 2.5, 1.0, 0),
     ("class_pad_r17", lambda: (np.random.default_rng(4).uniform(size=(90, 150)) < 0.5).astype(np.uint8), 5.5, 1.0, 0),
     ("tall300x40_r3", lambda: (np.random.default_rng(5).uniform(size=(300, 40)) < 0.2).astype(np.uint8), 1.0, 2.0, 0),
+    # largest aligned radius class of the 8-bit path, gray levels up to 255
+    ("gray160x210_r30", lambda: S.gray_gaussians((7, 1), H=160, W=210, n=10, major=(8, 40)), 10.0, 1 / 255, 0),
+    # radius 32 with every weight 255: the largest row-pass values the FP16 split must hold
+    ("const255_70x300_r32", lambda: np.full((70, 300), 255, np.uint8), 10.6, 1.0, 0),
+    # tall enough for the single-image launch to split the rows into many segments
+    ("segments700x150_r9", lambda: (np.random.default_rng(6).uniform(size=(700, 150)) < 0.4).astype(np.uint8), 3.0, 1.0, 0),
 ]
 
 
