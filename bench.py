@@ -56,6 +56,191 @@ def profile_figures(group: str):
         return None
 
 
+def _pool_init():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
+
+
+def _oracle_fit(args):
+    import oracle as O
+    weights, w0, sigma, R, iters = args
+    O.fit_lattice(weights, w0, sigma, R, iters)
+    return 1
+
+
+def cpu_legs(cases, seconds):
+    """The FP64 oracle on the host cores, run before the GPU is touched: the
+    lattice variant on one core (the reported baseline) and on every core of
+    the process's affinity set, and one sweep of the original point-set
+    update beside one lattice sweep on a sample stratified by N*M."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+
+    n = len(cases)
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        k = 0
+        while k < n and time.perf_counter() - t < seconds:
+            c = cases[k]
+            O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters)
+            k += 1
+        el = time.perf_counter() - t
+    cpu = {"value": k / el, "unit": "images/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {k} of the {n} silhouettes (same sizes, M, sigma, 100 sweeps), "
+                     f"FP64 NumPy lattice variant, {el:.1f}s"}
+    print(f"[bench] oracle on one core: {k} images in {el:.1f}s", file=sys.stderr, flush=True)
+
+    ctx = {"cpu_model": None, "cores_available": len(os.sched_getaffinity(0))}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                ctx["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    P = ctx["cores_available"]
+    with mp.get_context("fork").Pool(P, initializer=_pool_init) as pool:
+        t = time.perf_counter()
+        k2 = 0
+        while k2 < n and time.perf_counter() - t < seconds / 2:
+            idx = range(k2, min(n, k2 + P))
+            pool.map(_oracle_fit, [(cases[i].weights, cases[i].w0, cases[i].sigma, cases[i].R, cases[i].iters)
+                                   for i in idx])
+            k2 += len(idx)
+        el2 = time.perf_counter() - t
+    ctx["lattice_all_cores"] = {"value": k2 / el2, "unit": "images/s", "cores": P,
+                                "sample": f"first {k2} silhouettes, one image per process, {el2:.1f}s"}
+    print(f"[bench] oracle on {P} cores: {k2} images in {el2:.1f}s", file=sys.stderr, flush=True)
+
+    # original eq. (4) over the point set vs the lattice sweep, one sweep each
+    npts = np.array([int(np.count_nonzero(c.img)) * c.M for c in cases], dtype=np.float64)
+    order = np.argsort(npts, kind="stable")
+    strata = [int(order[int((i + 0.5) * n / 14)]) for i in range(14)] if n >= 14 else list(range(n))
+    t_orig = t_lat = 0.0
+    done = 0
+    with threadpool_limits(limits=1):
+        t_all = time.perf_counter()
+        for i in strata:
+            if time.perf_counter() - t_all > seconds:
+                break
+            c = cases[i]
+            X = np.argwhere(c.img > 0).astype(np.float64)
+            h = c.weights[c.img > 0]
+            xi, om = O.widths(c.sigma)
+            t = time.perf_counter()
+            O.original_step(X, h, c.w0, xi, om)
+            t_orig += time.perf_counter() - t
+            maps = O.lattice_maps(c.weights, c.sigma, c.R)
+            t = time.perf_counter()
+            O.lattice_step(maps, c.w0, c.sigma)
+            t_lat += time.perf_counter() - t
+            done += 1
+    ctx["original_vs_lattice_sweep"] = {
+        "images": done, "stratified_by": "on-pixels x M",
+        "original_s_per_sweep": t_orig / max(done, 1), "lattice_s_per_sweep": t_lat / max(done, 1),
+        "ratio": t_orig / t_lat if t_lat > 0 else None,
+        "original_images_per_s_extrapolated_100_sweeps": done / (100.0 * t_orig) if t_orig > 0 else None}
+    return cpu, ctx
+
+
+def gpu_extras(dev, cases, itc, synth):
+    """Secondary measurements: device copy and fill rates, the convolution per
+    sigma class of the silhouette batch, the single-image workloads (512^2 and
+    2048^2) end to end, and the convolution of the 64-image 1024^2 batch."""
+    import torch
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    out = {}
+    nb = 1 << 30
+    a = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    t = timed(lambda: b.copy_(a))
+    out["copy_gbs"] = 2.0 * nb / t / 1e9
+    t = timed(lambda: a.fill_(0.5))
+    out["fill_gbs"] = nb / t / 1e9
+    del a, b
+
+    def mx_flops_per_px(R):
+        ra = (R + 7) // 8 * 8
+        k = (16 + 2 * ra + 31) // 32 * 32
+        return 16.0 * (k // 32) * 16384.0 / 256.0
+
+    classes = []
+    for sigma in sorted({c.sigma for c in cases}):
+        sub = [c for c in cases if c.sigma == sigma]
+        p = itc.BatchPlan([torch.from_numpy(c.img) for c in sub], [c.M for c in sub], [c.sigma for c in sub],
+                          [c.iters for c in sub], device=dev)
+        t = timed(p.precompute)
+        px = float(sum(c.img.size for c in sub))
+        gbs = 13.0 * px / t / 1e9
+        classes.append({"sigma": sigma, "R": sub[0].R, "images": len(sub), "pixels": int(px), "ms": t * 1e3,
+                        "gbs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS, "frac_copy": gbs / out["copy_gbs"],
+                        "mfma_tflops": mx_flops_per_px(sub[0].R) * px / t / 1e12})
+        del p
+    out["conv_per_sigma"] = classes
+
+    singles = []
+    lib = itc.load()
+    for c in (synth.config2_case(0), synth.config4_case(0)):
+        img = torch.from_numpy(c.img).to(dev)
+        maps = itc.precompute(img, c.sigma, scale=c.scale)
+        w0 = torch.from_numpy(c.w0).to(dev, torch.float32)
+        wout = torch.empty_like(w0)
+        dtr = torch.empty(c.iters + 1, dtype=torch.float64, device=dev)
+        dn = torch.empty(1, dtype=torch.int32, device=dev)
+
+        def conv():
+            itc.precompute(img, c.sigma, scale=c.scale, out=maps)
+
+        def run():
+            conv()
+            itc._check(lib.itc_lattice_fit(itc.ctypes.byref(maps.desc), itc._ptr(maps.buf), itc._ptr(maps.s_x),
+                                           c.M, itc._ptr(w0), c.iters, -1.0, itc._ptr(wout), itc._ptr(dtr),
+                                           itc._ptr(dn), itc._stream()))
+
+        graphs = []
+        for fn in (conv, run):
+            s = torch.cuda.Stream(device=dev)
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                fn()
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            graphs.append(g)
+        t_conv = timed(graphs[0].replay)
+        t_run = timed(graphs[1].replay)
+        singles.append({"workload": c.name, "H": int(c.img.shape[0]), "W": int(c.img.shape[1]), "M": c.M,
+                        "sigma": c.sigma, "sweeps": c.iters, "images_per_s": 1.0 / t_run, "ms": t_run * 1e3,
+                        "conv_ms": t_conv * 1e3, "conv_gbs": 13.0 * c.img.size / t_conv / 1e9})
+        del maps, graphs
+    out["single_image"] = singles
+
+    c5 = synth.config5_cases(64)
+    p = itc.BatchPlan([torch.from_numpy(c.img) for c in c5], [c.M for c in c5], [c.sigma for c in c5],
+                      [c.iters for c in c5], device=dev)
+    t = timed(p.precompute)
+    px = float(sum(c.img.size for c in c5))
+    out["conv_gray1024x64"] = {"images": len(c5), "pixels": int(px), "ms": t * 1e3, "gbs": 13.0 * px / t / 1e9,
+                               "frac_hbm_peak": 13.0 * px / t / 1e9 / HBM_PEAK_GBS}
+    del p
+    return out
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -65,6 +250,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle leg")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-per-image", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the secondary measurements (copy peak, per-sigma conv, single-image workloads)")
     p.add_argument("--eager", action="store_true",
                    help="launch on the stream instead of replaying a HIP graph (for counter profiling)")
     p.add_argument("--copy-calib-mib", type=int, default=0,
@@ -85,23 +272,28 @@ def main():
 
     from paper_1310_7114_amd import itc, synth
 
-    itc.load()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    if args.copy_calib_mib > 0:  # a plain copy kernel of known size, for counter calibration
-        n = args.copy_calib_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
     t0 = time.time()
     cases = synth.config3_cases(args.images)
     print(f"[bench] generated {len(cases)} silhouettes in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     n = len(cases)
     npx = int(sum(c.img.size for c in cases))
+    # ---------------- oracle on the host cores (before the GPU is touched) ----------------
+    cpu, cpu_context = None, None
+    if not args.no_cpu:
+        cpu, cpu_context = cpu_legs(cases, args.cpu_seconds)
+
+    itc.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calib_mib > 0:  # a plain copy kernel of known size, for counter calibration
+        nel = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     plan = itc.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
                          [c.sigma for c in cases], [c.iters for c in cases], device=dev)
     w0 = plan.pack_codebooks([c.w0 for c in cases], device=dev)
@@ -204,22 +396,10 @@ def main():
                      "launches": "precompute (2 kernels) + fit (1 kernel) per image, one stream, HIP graph"}
         print(f"[bench] per-image loop {pi_s * 1e3:.1f} ms per pass", file=sys.stderr, flush=True)
 
-    # ---------------- oracle on the host cores ----------------
-    cpu = None
-    if not args.no_cpu:
-        import oracle as O
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):
-            t = time.perf_counter()
-            k = 0
-            while k < n and time.perf_counter() - t < args.cpu_seconds:
-                c = cases[k]
-                O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters)
-                k += 1
-            el = time.perf_counter() - t
-        cpu = {"value": k / el, "unit": "images/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {k} of the {n} silhouettes (same sizes, M, sigma, 100 sweeps), "
-                         f"FP64 NumPy lattice variant, {el:.1f}s"}
+    extras = None
+    if not args.no_extras:
+        extras = gpu_extras(dev, cases, itc, synth)
+        print("[bench] secondary measurements done", file=sys.stderr, flush=True)
 
     value = n / step_s
     out = {
@@ -253,6 +433,8 @@ def main():
                      "direct_form_tflops": conv_tfs,
                      "kernel": "conv_mx_tiles_kernel (one launch per aligned radius)"},
         "cpu_baseline": cpu,
+        "cpu_context": cpu_context,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -100,9 +100,11 @@ int64_t itc_lattice_map_pitch(const itc_lattice_desc* d);
 /*
  * Bytes of the maps buffer for `d`, 0 if `d` is invalid. Layout (all in the
  * real type): plane A, then plane M_u, then plane M_v, each height x
- * map_pitch row-major; then a trailer of ceil(width/64) x ceil(height/8) x 64
- * partial sums of S_X (library-internal). The size is a multiple of 256
- * bytes; the buffer must be 256-byte aligned.
+ * map_pitch row-major; then a library-internal trailer: ceil(width/64) x
+ * ceil(height/8) x 64 partial sums of S_X in the real type, and after them
+ * (8-byte aligned) ceil(width/64) x ceil(ceil(height/8)/64) FP64 block sums
+ * of those partials. The size is a multiple of 256 bytes; the buffer must be
+ * 256-byte aligned.
  */
 size_t itc_lattice_maps_bytes(const itc_lattice_desc* d);
 

@@ -357,12 +357,55 @@ __global__ void __launch_bounds__(CONV_NT) conv_tiles_kernel(const ImageDesc* __
   }
 }
 
-// S_X of one image from its partials (fixed summation order, FP64).
+// S_X = sum over the lattice of h A, from the partials the convolution
+// leaves per strip, 8-row group and lane. First level: block b of an image
+// (strip b / nb, groups SX_GROUPS (b mod nb) ..) is summed in a fixed order
+// into one FP64 value; second level: the block values in order. Both
+// levels depend only on the image shape, so every path gets the same bits.
 template <typename T>
-__global__ void __launch_bounds__(256) sx_finalize_kernel(ImageDesc im, const char* mbase, double* s_x) {
+__device__ __forceinline__ void sx_block_sum(const ImageDesc& im, char* mbase, int b, double* red) {
+  const int nb = sx_blocks_per_strip(im.H);
+  const int strip = b / nb, g0 = (b - strip * nb) * SX_GROUPS;
+  const int ng = min(SX_GROUPS, im.ngroups - g0);
+  const T* part = reinterpret_cast<const T*>(mbase + im.map_off + im.part_off) +
+                  ((int64_t)strip * im.ngroups + g0) * CONV_TW;
+  // thread t adds partials t, t + 256, ... in order; all loads are issued first
+  constexpr int PER = SX_GROUPS * CONV_TW / 256;
+  const int n = ng * CONV_TW;
+  T v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = (int)threadIdx.x + 256 * k;
+    v[k] = i < n ? part[i] : (T)0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) s += (double)v[k];
+  s = block_reduce_fixed(s, red);
+  if (threadIdx.x == 0) reinterpret_cast<double*>(mbase + im.map_off + im.sx_off)[b] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) sx_blocks_kernel(ImageDesc im, char* mbase) {
   __shared__ double red[4];
-  const T* part = reinterpret_cast<const T*>(mbase + im.map_off + im.part_off);
-  const double s = block_sum_fixed(part, (int64_t)im.nstrips * im.ngroups * CONV_TW, red);
+  sx_block_sum<T>(im, mbase, blockIdx.x, red);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) sx_blocks_batched_kernel(const ImageDesc* __restrict__ images,
+                                                                const SxBlock* __restrict__ blocks, int nblocks,
+                                                                char* mbase) {
+  __shared__ double red[4];
+  for (int k = blockIdx.x; k < nblocks; k += gridDim.x) {
+    const SxBlock sb = blocks[k];
+    sx_block_sum<T>(images[sb.img], mbase, sb.b, red);
+  }
+}
+
+__global__ void __launch_bounds__(256) sx_total_kernel(ImageDesc im, const char* mbase, double* s_x) {
+  __shared__ double red[4];
+  const double* blk = reinterpret_cast<const double*>(mbase + im.map_off + im.sx_off);
+  const double s = block_sum_fixed(blk, (int64_t)im.nstrips * sx_blocks_per_strip(im.H), red);
   if (threadIdx.x == 0) *s_x = s;
 }
 
@@ -452,10 +495,23 @@ int conv_tiles_blocks_per_cu(bool f64, int rclass) {
 
 hipError_t launch_sx_finalize(bool f64, const ImageDesc& img, const void* maps, double* s_x,
                               hipStream_t s) {
+  const dim3 grid((unsigned)n_sx_blocks(img.H, img.W));
   if (f64)
-    hipLaunchKernelGGL(sx_finalize_kernel<double>, dim3(1), dim3(256), 0, s, img, (const char*)maps, s_x);
+    hipLaunchKernelGGL(sx_blocks_kernel<double>, grid, dim3(256), 0, s, img, (char*)maps);
   else
-    hipLaunchKernelGGL(sx_finalize_kernel<float>, dim3(1), dim3(256), 0, s, img, (const char*)maps, s_x);
+    hipLaunchKernelGGL(sx_blocks_kernel<float>, grid, dim3(256), 0, s, img, (char*)maps);
+  hipLaunchKernelGGL(sx_total_kernel, dim3(1), dim3(256), 0, s, img, (const char*)maps, s_x);
+  return hipGetLastError();
+}
+
+hipError_t launch_sx_blocks_batched(bool f64, const ImageDesc* d_images, const SxBlock* d_blocks, int nblocks,
+                                    void* maps, int grid, hipStream_t s) {
+  if (f64)
+    hipLaunchKernelGGL(sx_blocks_batched_kernel<double>, dim3(grid), dim3(256), 0, s, d_images, d_blocks, nblocks,
+                       (char*)maps);
+  else
+    hipLaunchKernelGGL(sx_blocks_batched_kernel<float>, dim3(grid), dim3(256), 0, s, d_images, d_blocks, nblocks,
+                       (char*)maps);
   return hipGetLastError();
 }
 

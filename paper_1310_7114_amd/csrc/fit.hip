@@ -372,8 +372,10 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
   for (int ii = blockIdx.x; ii < fa.n; ii += gridDim.x) {
     const int i = order[ii];
     const ImageDesc im = images[i];
-    const T* part = reinterpret_cast<const T*>((const char*)fa.maps + im.map_off + im.part_off);
-    const double s_x = fa.s_x_in ? fa.s_x_in[i] : block_sum_fixed(part, (int64_t)im.nstrips * im.ngroups * CONV_TW, red);
+    // S_X from the block sums of its partials, written with the maps
+    const double* sxb = reinterpret_cast<const double*>((const char*)fa.maps + im.map_off + im.sx_off);
+    const double s_x =
+        fa.s_x_in ? fa.s_x_in[i] : block_sum_fixed(sxb, (int64_t)im.nstrips * sx_blocks_per_strip(im.H), red);
     if (threadIdx.x == 0 && fa.s_x_out) fa.s_x_out[i] = s_x;
     FitImageArgs a;
     a.mbase = (const char*)fa.maps;

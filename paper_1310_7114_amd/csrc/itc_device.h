@@ -136,11 +136,10 @@ __device__ __forceinline__ void buf_store(T v, rsrc_t r, uint32_t voff, uint32_t
 // multiple of 64): thread t adds t, t+nt, ...; then each wave by a fixed xor
 // tree; then the waves in order. `red` is shared scratch of nt/64 doubles.
 // Every thread gets the total.
-template <typename P>
-__device__ inline double block_sum_fixed(const P* p, int64_t n, double* red) {
+// The workgroup total of one FP64 value per thread: each wave by a fixed xor
+// tree, then the waves in order. Every thread gets the total.
+__device__ inline double block_reduce_fixed(double s, double* red) {
   const int nt = blockDim.x, tid = threadIdx.x;
-  double s = 0.0;
-  for (int64_t i = tid; i < n; i += nt) s += (double)p[i];
   s = wave_sum(s);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
@@ -148,6 +147,14 @@ __device__ inline double block_sum_fixed(const P* p, int64_t n, double* red) {
   for (int w = 0; w < nt / 64; ++w) t += red[w];
   __syncthreads();
   return t;
+}
+
+template <typename P>
+__device__ inline double block_sum_fixed(const P* p, int64_t n, double* red) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = tid; i < n; i += nt) s += (double)p[i];
+  return block_reduce_fixed(s, red);
 }
 
 }  // namespace itc

@@ -36,10 +36,16 @@ inline int radius_class(int R, bool f64) {
 }
 
 inline int64_t map_pitch_of(int W) { return ((int64_t)W + 63) / 64 * 64; }
-inline int n_strips(int W) { return (W + CONV_TW - 1) / CONV_TW; }
-inline int n_groups(int H) { return (H + CONV_GROUP - 1) / CONV_GROUP; }
+__host__ __device__ inline int n_strips(int W) { return (W + CONV_TW - 1) / CONV_TW; }
+__host__ __device__ inline int n_groups(int H) { return (H + CONV_GROUP - 1) / CONV_GROUP; }
 // S_X partials: one per (strip, CONV_GROUP-row group, lane), in the real type.
 inline int64_t n_partials(int H, int W) { return (int64_t)n_strips(W) * n_groups(H) * CONV_TW; }
+// S_X in two fixed-order levels: block b of an image sums the partials of
+// SX_GROUPS consecutive groups of one strip into one FP64 value (stored after
+// the partials); S_X is the fixed-order sum of those values.
+constexpr int SX_GROUPS = 64;
+__host__ __device__ inline int sx_blocks_per_strip(int H) { return (n_groups(H) + SX_GROUPS - 1) / SX_GROUPS; }
+__host__ __device__ inline int64_t n_sx_blocks(int H, int W) { return (int64_t)n_strips(W) * sx_blocks_per_strip(H); }
 
 // One image as the kernels see it. Offsets are in bytes from the batch bases.
 struct ImageDesc {
@@ -48,6 +54,7 @@ struct ImageDesc {
   int64_t map_off;      // maps of this image (planes A, Mu, Mv, then partials)
   int64_t map_pitch;    // elements per map row
   int64_t part_off;     // byte offset of the S_X partials inside the maps
+  int64_t sx_off;       // byte offset of the FP64 block sums of the partials
   int64_t w_off;        // codebook offset, codevectors
   double scale;         // h = scale * stored
   double sigma;
@@ -95,6 +102,14 @@ hipError_t launch_conv_mx_tiles(int ra, const ImageDesc* d_images, const ConvTil
 int conv_mx_blocks_per_cu(int ra);
 hipError_t launch_sx_finalize(bool f64, const ImageDesc& img, const void* maps, double* s_x,
                               hipStream_t s);
+// Block sums of the S_X partials of many images: one (image, block) pair
+// per entry of `blocks`.
+struct SxBlock {
+  int32_t img;
+  int32_t b;
+};
+hipError_t launch_sx_blocks_batched(bool f64, const ImageDesc* d_images, const SxBlock* d_blocks, int nblocks,
+                                    void* maps, int grid, hipStream_t s);
 
 struct FitArgs {
   const void* maps;      // batch base of maps

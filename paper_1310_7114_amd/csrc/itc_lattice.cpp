@@ -77,7 +77,8 @@ itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out) {
   const uint64_t esz = d->weight_dtype == ITC_U8 ? 1 : (d->weight_dtype == ITC_F32 ? 4 : 8);
   const uint64_t img_bytes = (uint64_t)d->height * (uint64_t)d->pitch * esz;
   const uint64_t map_bytes = (uint64_t)3 * d->height * (uint64_t)itc::map_pitch_of(d->width) * (f64 ? 8 : 4) +
-                             (uint64_t)itc::n_partials(d->height, d->width) * (f64 ? 8 : 4);
+                             (uint64_t)itc::n_partials(d->height, d->width) * (f64 ? 8 : 4) + 8 +
+                             (uint64_t)itc::n_sx_blocks(d->height, d->width) * 8;
   if (img_bytes >= (1ull << 31) || map_bytes >= (1ull << 31))
     return fail(ITC_E_UNSUPPORTED, "image (%llu B) or maps (%llu B) exceed 2 GiB", (unsigned long long)img_bytes,
                 (unsigned long long)map_bytes);
@@ -90,9 +91,14 @@ size_t planes_bytes(const itc_lattice_desc& d) {
   return (size_t)3 * d.height * itc::map_pitch_of(d.width) * real_size(d.real_dtype);
 }
 
-size_t maps_bytes_of(const itc_lattice_desc& d) {
+// FP64 block sums of the S_X partials follow the partials, 8-byte aligned.
+size_t sx_offset(const itc_lattice_desc& d) {
   const size_t part = (size_t)itc::n_partials(d.height, d.width) * real_size(d.real_dtype);
-  return (planes_bytes(d) + part + 255) / 256 * 256;
+  return (planes_bytes(d) + part + 7) / 8 * 8;
+}
+
+size_t maps_bytes_of(const itc_lattice_desc& d) {
+  return (sx_offset(d) + (size_t)itc::n_sx_blocks(d.height, d.width) * sizeof(double) + 255) / 256 * 256;
 }
 
 ImageDesc make_image(const itc_lattice_desc& d, int R, int rc) {
@@ -101,6 +107,7 @@ ImageDesc make_image(const itc_lattice_desc& d, int R, int rc) {
   im.pitch = d.pitch;
   im.map_pitch = itc::map_pitch_of(d.width);
   im.part_off = (int64_t)planes_bytes(d);
+  im.sx_off = (int64_t)sx_offset(d);
   im.scale = d.weight_scale;
   im.sigma = d.sigma;
   im.H = d.height;
@@ -144,6 +151,9 @@ struct itc_plan {
   ConvTile* d_tiles = nullptr;
   int32_t* d_order = nullptr;
   itc::GradTile* d_gtiles = nullptr;
+  std::vector<itc::SxBlock> sxblocks;  // S_X block sums of every image
+  int sx_grid = 1;
+  itc::SxBlock* d_sxblocks = nullptr;
 };
 
 extern "C" {
@@ -355,6 +365,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     fit_cost[i] = (double)(im.iters + 1) * im.M * (im.M + 16.0);
     for (int u0 = 0; u0 < im.H; u0 += 64)
       for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
+    for (int64_t sb = 0; sb < itc::n_sx_blocks(im.H, im.W); ++sb) p->sxblocks.push_back(itc::SxBlock{i, (int32_t)sb});
   }
   for (int rc = 0; rc < NKEYS; ++rc) {
     if (by_class[rc].empty()) continue;
@@ -380,6 +391,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   if (fper < 1) fper = 1;
   p->fit_grid = std::min(p->n, fper * cus);
   p->grad_grid = std::min((int)p->gtiles.size(), 4 * cus);
+  p->sx_grid = std::min((int)p->sxblocks.size(), 8 * cus);
 
   hipError_t e = hipMalloc(&p->d_images, sizeof(ImageDesc) * p->n);
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tiles.size()));
@@ -392,6 +404,10 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   if (e == hipSuccess) e = hipMalloc(&p->d_gtiles, sizeof(itc::GradTile) * p->gtiles.size());
   if (e == hipSuccess)
     e = hipMemcpy(p->d_gtiles, p->gtiles.data(), sizeof(itc::GradTile) * p->gtiles.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_sxblocks, sizeof(itc::SxBlock) * p->sxblocks.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_sxblocks, p->sxblocks.data(), sizeof(itc::SxBlock) * p->sxblocks.size(),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     itc_lattice_plan_destroy(p);
     return device_fail(e, "plan upload");
@@ -446,6 +462,7 @@ void itc_lattice_plan_destroy(itc_plan* p) {
   if (p->d_tiles) (void)hipFree(p->d_tiles);
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_gtiles) (void)hipFree(p->d_gtiles);
+  if (p->d_sxblocks) (void)hipFree(p->d_sxblocks);
   delete p;
 }
 
@@ -458,6 +475,9 @@ itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void
                                           (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "batched convolution launch");
   }
+  hipError_t e = itc::launch_sx_blocks_batched(false, p->d_images, p->d_sxblocks, (int)p->sxblocks.size(), maps,
+                                               p->sx_grid, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "S_X block sums launch");
   return ok();
 }
 
