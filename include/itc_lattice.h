@@ -68,6 +68,8 @@ typedef enum { ITC_U8 = 0, ITC_F32 = 1, ITC_F64 = 2 } itc_dtype;
 #define ITC_MAX_RADIUS_F32 32
 #define ITC_MAX_RADIUS_F64 16
 #define ITC_MAX_CODEVECTORS 1024
+#define ITC_MAX_CHAMFER_WIDTH 16384 /* widest image the chamfer transform accepts */
+#define ITC_MAX_CHAMFER_STEP 64     /* largest orthogonal step cost of the chamfer mask */
 
 /*
  * One lattice problem. The weight image (Section 3.2 binary image, or
@@ -159,6 +161,26 @@ itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void
                                            const double* grad_d, void* grad_w, void* grad_weights,
                                            void* stream);
 
+/*
+ * Section 5 weighting: the chamfer distance transform T(X) of a binary image
+ * (Borgefors' chamfer transforms, named there for P = T(X) * G_xi). T is the
+ * least cost of an 8-connected path from each foreground pixel (stored value
+ * != 0) to the background, orthogonal steps costing `a` and diagonal steps
+ * `b` (3 and 4 give the usual 3-4 chamfer, T / a ~ Euclidean pixels);
+ * background pixels get 0 and everything outside the lattice is background.
+ *   d        height, width and pitch of the binary image; weight_dtype must be
+ *            ITC_U8 (sigma and the other fields are not used);
+ *   x        device, height x pitch bytes (read);
+ *   t_out    device, height x pitch floats (written; columns >= width are
+ *            left untouched), exact integer chamfer costs. It can be passed
+ *            as an ITC_F32 weight image with the same pitch and
+ *            weight_scale = 1/a.
+ * Requires 1 <= a <= b <= 2a, a <= ITC_MAX_CHAMFER_STEP and
+ * width <= ITC_MAX_CHAMFER_WIDTH. Asynchronous on `stream`; no allocation.
+ */
+itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t a, int32_t b,
+                               float* t_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: n independent images of uneven size, each with its own M,
  * sigma and iteration count, in flat device buffers. A plan is built once per
@@ -213,6 +235,15 @@ itc_status itc_lattice_run_batched(itc_plan* p, const void* weights, void* maps,
 itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps, const double* s_x,
                                                    const void* w, const double* grad_d, void* grad_w,
                                                    void* grad_weights, void* stream);
+
+/*
+ * Chamfer transform (itc_lattice_chamfer) of every image of a plan whose
+ * weights are ITC_U8. Image i is read at byte offset weight_off[i] of
+ * `weights` and written at float offset weight_off[i] of `t_out` (the same
+ * pitch), so t_out holds 4x the bytes of the weights buffer. Two launches.
+ */
+itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t a, int32_t b, float* t_out,
+                                       void* stream);
 
 /* Number of images in the plan, or -1 for NULL. */
 int32_t itc_lattice_plan_size(const itc_plan* p);

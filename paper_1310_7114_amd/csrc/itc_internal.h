@@ -108,6 +108,17 @@ struct SxBlock {
   int32_t img;
   int32_t b;
 };
+// Chamfer transform: a task is (image, strip) for the column pass and
+// (image, first row) for the row pass.
+struct ChamferTask {
+  int32_t img;
+  int32_t pos;
+};
+int chamfer_rows_per_task();
+hipError_t launch_chamfer(const ImageDesc& im, const void* x, float* t, int a, int b, hipStream_t s);
+hipError_t launch_chamfer_batched(const ImageDesc* d_images, const ChamferTask* d_cols, int ncols,
+                                  const ChamferTask* d_rows, int nrows, int w_max, const void* x, float* t, int a,
+                                  int b, int grid_cols, int grid_rows, hipStream_t s);
 hipError_t launch_sx_blocks_batched(bool f64, const ImageDesc* d_images, const SxBlock* d_blocks, int nblocks,
                                     void* maps, int grid, hipStream_t s);
 

@@ -154,6 +154,12 @@ struct itc_plan {
   std::vector<itc::SxBlock> sxblocks;  // S_X block sums of every image
   int sx_grid = 1;
   itc::SxBlock* d_sxblocks = nullptr;
+  // chamfer transform: column-pass strips and row-pass row groups
+  std::vector<itc::ChamferTask> ch_cols, ch_rows;
+  bool all_u8 = true;
+  int w_max = 0;
+  itc::ChamferTask* d_ch_cols = nullptr;
+  itc::ChamferTask* d_ch_rows = nullptr;
 };
 
 extern "C" {
@@ -366,6 +372,10 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     for (int u0 = 0; u0 < im.H; u0 += 64)
       for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
     for (int64_t sb = 0; sb < itc::n_sx_blocks(im.H, im.W); ++sb) p->sxblocks.push_back(itc::SxBlock{i, (int32_t)sb});
+    p->all_u8 = p->all_u8 && im.wdtype == ITC_U8;
+    p->w_max = std::max(p->w_max, im.W);
+    for (int st2 = 0; st2 < im.nstrips; ++st2) p->ch_cols.push_back(itc::ChamferTask{i, st2});
+    for (int r0 = 0; r0 < im.H; r0 += itc::chamfer_rows_per_task()) p->ch_rows.push_back(itc::ChamferTask{i, r0});
   }
   for (int rc = 0; rc < NKEYS; ++rc) {
     if (by_class[rc].empty()) continue;
@@ -404,6 +414,14 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   if (e == hipSuccess) e = hipMalloc(&p->d_gtiles, sizeof(itc::GradTile) * p->gtiles.size());
   if (e == hipSuccess)
     e = hipMemcpy(p->d_gtiles, p->gtiles.data(), sizeof(itc::GradTile) * p->gtiles.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_ch_cols, sizeof(itc::ChamferTask) * p->ch_cols.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_ch_cols, p->ch_cols.data(), sizeof(itc::ChamferTask) * p->ch_cols.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_ch_rows, sizeof(itc::ChamferTask) * p->ch_rows.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_ch_rows, p->ch_rows.data(), sizeof(itc::ChamferTask) * p->ch_rows.size(),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_sxblocks, sizeof(itc::SxBlock) * p->sxblocks.size());
   if (e == hipSuccess)
     e = hipMemcpy(p->d_sxblocks, p->sxblocks.data(), sizeof(itc::SxBlock) * p->sxblocks.size(),
@@ -463,6 +481,8 @@ void itc_lattice_plan_destroy(itc_plan* p) {
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_gtiles) (void)hipFree(p->d_gtiles);
   if (p->d_sxblocks) (void)hipFree(p->d_sxblocks);
+  if (p->d_ch_cols) (void)hipFree(p->d_ch_cols);
+  if (p->d_ch_rows) (void)hipFree(p->d_ch_rows);
   delete p;
 }
 
@@ -501,6 +521,53 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
   a.write_w = 1;
   hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, (hipStream_t)stream, nullptr);
   if (e != hipSuccess) return device_fail(e, "batched fit launch");
+  return ok();
+}
+
+static itc_status check_chamfer_mask(int32_t a, int32_t b) {
+  if (a < 1 || a > ITC_MAX_CHAMFER_STEP || b < a || b > 2 * a)
+    return fail(ITC_E_ARG, "chamfer steps need 1 <= a <= b <= 2a and a <= %d (got a=%d, b=%d)",
+                ITC_MAX_CHAMFER_STEP, a, b);
+  return ITC_OK;
+}
+
+itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t a, int32_t b, float* t_out,
+                               void* stream) {
+  if (!d || !x || !t_out) return fail(ITC_E_NULL, "desc, x and t_out must be non-NULL");
+  if (d->height < 1 || d->width < 1) return fail(ITC_E_ARG, "height and width must be >= 1");
+  if (d->pitch < d->width) return fail(ITC_E_ARG, "pitch %lld < width %d", (long long)d->pitch, d->width);
+  if (d->weight_dtype != ITC_U8) return fail(ITC_E_ARG, "the chamfer transform takes ITC_U8 images");
+  if (d->width > ITC_MAX_CHAMFER_WIDTH)
+    return fail(ITC_E_UNSUPPORTED, "width %d exceeds %d", d->width, ITC_MAX_CHAMFER_WIDTH);
+  if ((uint64_t)d->height * (uint64_t)d->pitch >= (1ull << 31))
+    return fail(ITC_E_UNSUPPORTED, "image exceeds 2^31 elements");
+  itc_status st = check_chamfer_mask(a, b);
+  if (st != ITC_OK) return st;
+  ImageDesc im;
+  std::memset(&im, 0, sizeof im);
+  im.H = d->height;
+  im.W = d->width;
+  im.pitch = d->pitch;
+  hipError_t e = itc::launch_chamfer(im, x, t_out, a, b, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "chamfer launch");
+  return ok();
+}
+
+itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t a, int32_t b, float* t_out,
+                                       void* stream) {
+  if (!p || !weights || !t_out) return fail(ITC_E_NULL, "plan, weights and t_out must be non-NULL");
+  if (!p->all_u8) return fail(ITC_E_ARG, "the chamfer transform takes ITC_U8 images");
+  if (p->w_max > ITC_MAX_CHAMFER_WIDTH)
+    return fail(ITC_E_UNSUPPORTED, "width %d exceeds %d", p->w_max, ITC_MAX_CHAMFER_WIDTH);
+  itc_status st = check_chamfer_mask(a, b);
+  if (st != ITC_OK) return st;
+  const int cus = device_cus();
+  const int gc = std::min((int)p->ch_cols.size(), 16 * cus);
+  const int gr = std::min((int)p->ch_rows.size(), 4 * cus);
+  hipError_t e = itc::launch_chamfer_batched(p->d_images, p->d_ch_cols, (int)p->ch_cols.size(), p->d_ch_rows,
+                                             (int)p->ch_rows.size(), p->w_max, weights, t_out, a, b, gc, gr,
+                                             (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "batched chamfer launch");
   return ok();
 }
 

@@ -63,6 +63,8 @@ SIGNATURES = {
     "itc_lattice_fit_batched": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_divergence_backward_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "itc_lattice_chamfer": (ctypes.c_int, [_DP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "itc_lattice_chamfer_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_destroy": (None, [_P]),
     "itc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -203,6 +205,21 @@ def divergence_backward(maps: Maps, w: torch.Tensor, grad_d: torch.Tensor, want_
     return gw, gI
 
 
+def chamfer(x: torch.Tensor, a: int = 3, b: int = 4, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Chamfer distance transform of a (H, W) binary uint8 device image: float32 (H, W) of exact
+    integer chamfer costs (orthogonal step a, diagonal step b); T / a approximates pixels."""
+    if x.dim() != 2 or x.dtype != torch.uint8:
+        raise ValueError("x must be a (H, W) uint8 tensor")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    H, W = x.shape
+    desc = make_desc(H, W, 1.0, torch.uint8, torch.float32, 1.0, 0, pitch=x.stride(0))
+    if out is None:
+        out = torch.empty((H, x.stride(0)), dtype=torch.float32, device=x.device)
+    _check(load().itc_lattice_chamfer(ctypes.byref(desc), _ptr(x), int(a), int(b), _ptr(out), _stream()))
+    return out[:, :W]
+
+
 # ---------------------------------------------------------------------------
 # batched form
 # ---------------------------------------------------------------------------
@@ -218,7 +235,7 @@ class BatchPlan:
 
     def __init__(self, images: Optional[Sequence[torch.Tensor]], ms: Sequence[int], sigmas: Sequence[float],
                  iters: Sequence[int], scales: Optional[Sequence[float]] = None,
-                 radii: Optional[Sequence[int]] = None, device="cuda", _shapes=None, _dtype=None):
+                 radii: Optional[Sequence[int]] = None, device="cuda", _shapes=None, _dtype=None, _woffs=None):
         shapes = [tuple(im.shape) for im in images] if images is not None else list(_shapes)
         n = len(shapes)
         if n == 0:
@@ -230,6 +247,7 @@ class BatchPlan:
         self.n = n
         self.dtype = dt
         self.shapes = shapes
+        self.sigmas, self.scales, self.radii, self.iters_list = list(sigmas), scales, radii, [int(t) for t in iters]
         self.descs = (Desc * n)()
         wo, mo, wf, mlist, it = [], [], [], [], []
         woff = moff = foff = 0
@@ -237,7 +255,7 @@ class BatchPlan:
             if images is not None and images[i].dtype != dt:
                 raise ValueError("all images of a batch share one storage dtype")
             self.descs[i] = make_desc(H, W, sigmas[i], dt, torch.float32, scales[i], radii[i])
-            wo.append(woff)
+            wo.append(woff if _woffs is None else int(_woffs[i]))
             woff += H * W * esz if images is None else (H * W * esz + 255) // 256 * 256
             mo.append(moff)
             moff += maps_bytes(self.descs[i])
@@ -273,6 +291,24 @@ class BatchPlan:
         """Plan for a contiguous (B, H, W) weight stack and (B * M, 2) codebooks."""
         return cls(None, [M] * B, [sigma] * B, [iters] * B, [scale] * B, [radius] * B, device=device,
                    _shapes=[(H, W)] * B, _dtype=dtype)
+
+    def chamfer(self, a: int = 3, b: int = 4, weights=None, out=None) -> torch.Tensor:
+        """Chamfer transform of every (uint8, binary) image: a float32 buffer holding image i at element
+        offset weight_off[i], with the images' pitch."""
+        w = self._w(weights)
+        if out is None:
+            out = torch.empty(w.numel(), dtype=torch.float32, device=w.device)
+        _check(load().itc_lattice_chamfer_batched(self.handle, _ptr(w), int(a), int(b), _ptr(out), _stream()))
+        return out
+
+    def weighted(self, a: int = 3) -> "BatchPlan":
+        """A plan over the same images, codebooks, widths and sweeps whose weights are this plan's
+        chamfer transforms (float32, as written by `chamfer`), scaled by 1/a (Section 5)."""
+        if self.dtype != torch.uint8:
+            raise ValueError("the chamfer weighting starts from uint8 images")
+        return BatchPlan(None, self.ms, self.sigmas, self.iters_list, [1.0 / a] * self.n, self.radii,
+                         device=self.maps.device, _shapes=self.shapes, _dtype=torch.float32,
+                         _woffs=[4 * int(o) for o in self.weight_off])
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -106,6 +106,25 @@ def test_null_and_range_arguments(itc):
     lib.itc_lattice_plan_destroy(None)
 
 
+def test_chamfer_arguments(itc):
+    lib = itc.load()
+    P = ctypes.c_void_p(256)
+    ch = lib.itc_lattice_chamfer
+    d = itc.make_desc(16, 16, 1.0)
+    assert ch(None, P, 3, 4, P, None) == 1
+    assert ch(ctypes.byref(d), None, 3, 4, P, None) == 1
+    assert ch(ctypes.byref(d), P, 3, 4, None, None) == 1
+    for a, b in ((0, 0), (3, 2), (3, 7), (65, 65), (-1, 1)):
+        assert ch(ctypes.byref(d), P, a, b, P, None) == 2, (a, b)
+    df = itc.make_desc(16, 16, 1.0, weight_dtype=__import__("torch").float32)
+    assert ch(ctypes.byref(df), P, 3, 4, P, None) == 2             # binary images are ITC_U8
+    dw = itc.make_desc(2, 16385, 1.0)
+    assert ch(ctypes.byref(dw), P, 3, 4, P, None) == 3             # wider than ITC_MAX_CHAMFER_WIDTH
+    dp = itc.make_desc(4, 16, 1.0, pitch=8)
+    assert ch(ctypes.byref(dp), P, 3, 4, P, None) == 2             # pitch < width
+    assert lib.itc_lattice_chamfer_batched(None, P, 3, 4, P, None) == 1
+
+
 def test_plan_rejects_bad_batches(itc):
     lib = itc.load()
     h = ctypes.c_void_p()

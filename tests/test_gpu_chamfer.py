@@ -1,0 +1,129 @@
+"""Chamfer distance transform (Section 5 weighting) on the GPU vs the oracle's
+Borgefors two-pass propagation: integer costs, compared bit for bit; then the
+weighted fit P = T(X) * G_xi against the oracle's lattice fit on T / a."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1310_7114_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_img(seed, H, W, p):
+    return (np.random.default_rng(seed).uniform(size=(H, W)) < p).astype(np.uint8)
+
+
+def gpu_chamfer(itc, img, a=3, b=4, pitch=None):
+    H, W = img.shape
+    if pitch is None:
+        x = torch.from_numpy(img).cuda()
+    else:
+        buf = torch.zeros((H, pitch), dtype=torch.uint8, device="cuda")
+        buf[:, :W] = torch.from_numpy(img).cuda()
+        x = buf[:, :W]
+    t = itc.chamfer(x, a, b)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = [
+    ("ellipses64", lambda: S.config1_case(1).img),
+    ("shapes512", lambda: S.config2_case(0).img),
+    ("ragged37x1000", lambda: rand_img(1, 37, 1000, 0.93)),
+    ("tiny1x1_fg", lambda: np.ones((1, 1), np.uint8)),
+    ("tiny1x1_bg", lambda: np.zeros((1, 1), np.uint8)),
+    ("row1x300", lambda: rand_img(2, 1, 300, 0.97)),
+    ("col300x1", lambda: rand_img(3, 300, 1, 0.97)),
+    ("all_fg_70x129", lambda: np.ones((70, 129), np.uint8)),
+    ("all_bg_40x40", lambda: np.zeros((40, 40), np.uint8)),
+    ("gray_levels", lambda: S.gray_gaussians((7, 2), H=90, W=140, n=6, major=(10, 30))),
+]
+
+
+@pytest.mark.parametrize("name,build", CASES, ids=[c[0] for c in CASES])
+def test_chamfer_34(gpu_lib, name, build):
+    img = build()
+    ref = O.chamfer_transform(img, 3, 4)
+    got = gpu_chamfer(gpu_lib, img)
+    assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 2), (5, 7), (2, 3), (64, 100)])
+def test_chamfer_masks(gpu_lib, a, b):
+    img = rand_img(5, 61, 77, 0.9)
+    assert np.array_equal(gpu_chamfer(gpu_lib, img, a, b), O.chamfer_transform(img, a, b).astype(np.float32))
+
+
+def test_chamfer_pitch_and_widest(gpu_lib):
+    img = rand_img(6, 45, 200, 0.9)
+    assert np.array_equal(gpu_chamfer(gpu_lib, img, pitch=256), O.chamfer_transform(img).astype(np.float32))
+    wide = rand_img(7, 3, 16384, 0.99)  # the widest accepted row: 64 KB of LDS
+    assert np.array_equal(gpu_chamfer(gpu_lib, wide), O.chamfer_transform(wide).astype(np.float32))
+
+
+def test_chamfer_rejects_bad_masks(gpu_lib):
+    img = torch.ones((4, 4), dtype=torch.uint8, device="cuda")
+    for a, b in ((0, 0), (3, 2), (3, 7), (65, 65)):
+        with pytest.raises(gpu_lib.ItcError):
+            gpu_lib.chamfer(img, a, b)
+
+
+def test_chamfer_batched(gpu_lib):
+    """48 silhouettes in one plan: batched equals per-image bit for bit; two checked against the oracle."""
+    cases = S.config3_cases(indices=range(48))
+    plan = gpu_lib.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
+                             [c.sigma for c in cases], [c.iters for c in cases])
+    t = plan.chamfer()
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        H, W = c.img.shape
+        off = int(plan.weight_off[i])
+        ti = t[off: off + H * W].view(H, W)
+        assert torch.equal(ti, gpu_lib.chamfer(torch.from_numpy(c.img).cuda())), i
+    for i in (0, 17):
+        H, W = cases[i].img.shape
+        off = int(plan.weight_off[i])
+        got = t[off: off + H * W].view(H, W).cpu().numpy()
+        assert np.array_equal(got, O.chamfer_transform(cases[i].img).astype(np.float32)), i
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_weighted_fit_config1(gpu_lib, seed):
+    """Section 5: P = T(X) * G_xi with the 3-4 chamfer T; the fit on T / 3 matches the oracle."""
+    case = S.config1_case(seed)
+    x = torch.from_numpy(case.img).cuda()
+    t = gpu_lib.chamfer(x, 3, 4).contiguous()
+    m = gpu_lib.precompute(t, case.sigma, scale=1.0 / 3.0)
+    w, tr, done = gpu_lib.fit(m, torch.from_numpy(case.w0).cuda(), case.iters)
+    torch.cuda.synchronize()
+    weights = O.chamfer_transform(case.img, 3, 4) / 3.0
+    W_ref, tr_ref, _, _ = O.fit_lattice(weights, case.w0, case.sigma, case.R, case.iters)
+    w = w.cpu().double().numpy()
+    assert float(np.linalg.norm(w - W_ref, axis=1).max()) <= 1e-3
+    assert np.abs(tr.cpu().numpy() - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
+    # interior weighting pulls the codebook inward: it differs from the unweighted fit
+    W_plain, _, _, _ = O.fit_lattice(case.weights, case.w0, case.sigma, case.R, case.iters)
+    assert float(np.linalg.norm(W_ref - W_plain, axis=1).max()) > 0.1
+
+
+def test_weighted_batched_equals_per_image(gpu_lib):
+    """plan.weighted(): the chamfer-weighted batch equals the per-image weighted calls bit for bit."""
+    cases = S.config3_cases(indices=range(16))
+    plan = gpu_lib.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
+                             [c.sigma for c in cases], [c.iters for c in cases])
+    t = plan.chamfer()
+    wp = plan.weighted(3)
+    w0 = wp.pack_codebooks([c.w0 for c in cases])
+    w = torch.empty_like(w0)
+    d = torch.empty(len(cases), dtype=torch.float64, device="cuda")
+    wp.run(w0, w, d_out=d, weights=t)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        ti = gpu_lib.chamfer(torch.from_numpy(c.img).cuda()).contiguous()
+        m = gpu_lib.precompute(ti, c.sigma, scale=1.0 / 3.0)
+        wi, tr, _ = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda(), c.iters)
+        torch.cuda.synchronize()
+        assert torch.equal(wp.unpack(w, i), wi), i
+        assert float(d[i]) == float(tr[-1]), i
