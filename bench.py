@@ -142,6 +142,15 @@ def cpu_legs(cases, seconds):
         "original_s_per_sweep": t_orig / max(done, 1), "lattice_s_per_sweep": t_lat / max(done, 1),
         "ratio": t_orig / t_lat if t_lat > 0 else None,
         "original_images_per_s_extrapolated_100_sweeps": done / (100.0 * t_orig) if t_orig > 0 else None}
+    # Section 5: the oracle's two-pass chamfer transform on the first silhouettes
+    t = time.perf_counter()
+    k3, px3 = 0, 0
+    while k3 < n and time.perf_counter() - t < seconds / 5:
+        O.chamfer_transform(cases[k3].img, 3, 4)
+        px3 += cases[k3].img.size
+        k3 += 1
+    el3 = time.perf_counter() - t
+    ctx["chamfer_oracle"] = {"images": k3, "pixels_per_s": px3 / el3, "cores": 1}
     return cpu, ctx
 
 
@@ -229,6 +238,24 @@ def gpu_extras(dev, cases, itc, synth):
                         "conv_ms": t_conv * 1e3, "conv_gbs": 13.0 * c.img.size / t_conv / 1e9})
         del maps, graphs
     out["single_image"] = singles
+
+    # Section 5 weighting: chamfer transform of every silhouette, then the
+    # fit of the chamfer-weighted batch (weights T/3, FP32 convolution)
+    pu8 = itc.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
+                        [c.sigma for c in cases], [c.iters for c in cases], device=dev)
+    tch = pu8.chamfer()
+    t_ch = timed(lambda: pu8.chamfer(out=tch))
+    pw = pu8.weighted(3)
+    w0w = pw.pack_codebooks([c.w0 for c in cases], device=dev)
+    ww = torch.empty_like(w0w)
+    t_wrun = timed(lambda: pw.run(w0w, ww, weights=tch), reps=3)
+    npx_all = float(sum(c.img.size for c in cases))
+    out["chamfer_silhouettes"] = {"images": len(cases), "pixels": int(npx_all), "ms": t_ch * 1e3,
+                                  "gpx_per_s": npx_all / t_ch / 1e9,
+                                  "gbs_algorithmic": 5.0 * npx_all / t_ch / 1e9, "bytes_per_px": 5,
+                                  "weighted_fit_ms": t_wrun * 1e3,
+                                  "weighted_images_per_s": len(cases) / (t_ch + t_wrun)}
+    del pu8, pw, tch
 
     c5 = synth.config5_cases(64)
     p = itc.BatchPlan([torch.from_numpy(c.img) for c in c5], [c.M for c in c5], [c.sigma for c in c5],

@@ -18,7 +18,8 @@
 //   (rows -1 and H and columns -1 and W are background).
 //
 // Pass 1 (columns): one thread per column walks down and up the column and
-// writes g. Pass 2 (rows): a workgroup stages one row of g in LDS and every
+// writes g (columns of up to 1,024 rows are first packed into a bit mask, so
+// the image is read once and g written once). Pass 2 (rows): a workgroup stages one row of g in LDS and every
 // thread searches outward from its column, stopping once a |j - l| reaches
 // the best cost found (phi >= a |j - l|). Values are exact integers, stored
 // as FP32 so that T can feed the convolution as a weight image.
@@ -58,6 +59,59 @@ __device__ __forceinline__ void chamfer_cols(const uint8_t* __restrict__ x, int6
   }
 }
 
+// Pass 1 for columns of at most 32 * CH_WORDS rows: the column is read once
+// into a bit mask (bit k of word w: row 32w + k is foreground) and the first
+// background row at or after each word is found walking the words upwards;
+// then one walk down the rows writes g, each row needing only its own word.
+// Every LDS word belongs to one lane, so no synchronisation is needed.
+constexpr int CH_WORDS = 32;
+
+__device__ __forceinline__ void chamfer_cols_bits(const uint8_t* __restrict__ x, int64_t pitch,
+                                                  float* __restrict__ t, int H, int W, int v0,
+                                                  uint32_t* __restrict__ sbits, int32_t* __restrict__ snext) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int j = v0 + lane;
+  const bool col = j < W;
+  const uint8_t* xc = x + (col ? j : 0);
+  const int nw = (H + 31) / 32;
+  for (int w = 0; w < nw; ++w) {
+    uint32_t m = 0u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const int i = 32 * w + k;
+      const bool fg = col && i < H && xc[(int64_t)i * pitch] != 0;
+      m |= fg ? 1u << k : 0u;
+    }
+    sbits[w * 64 + lane] = m;  // rows >= H stay background
+  }
+  int nxt = H;  // row H is background
+  for (int w = nw - 1; w >= 0; --w) {
+    const uint32_t inv = ~sbits[w * 64 + lane];
+    if (inv) nxt = 32 * w + __builtin_ctz(inv);
+    snext[w * 64 + lane] = nxt;
+  }
+  if (!col) return;
+  float* tc = t + j;
+  int last = -1;  // row -1 is background
+  for (int w = 0; w < nw; ++w) {
+    const uint32_t m = sbits[w * 64 + lane];
+    const int after = w + 1 < nw ? snext[(w + 1) * 64 + lane] : H;
+    const int kn = min(32, H - 32 * w);
+    for (int k = 0; k < kn; ++k) {
+      const int i = 32 * w + k;
+      int g = 0;
+      if ((m >> k) & 1u) {
+        const uint32_t inv = ~m >> k;  // background rows at or after i within the word
+        const int down = inv ? i + __builtin_ctz(inv) : after;
+        g = min(i - last, down - i);
+      } else {
+        last = i;
+      }
+      tc[(int64_t)i * pitch] = (float)g;
+    }
+  }
+}
+
 // Pass 2 for rows r0 .. r0 + n - 1 (in place: a row of g is staged in LDS
 // before any of its T values is written).
 __device__ __forceinline__ void chamfer_rows(float* __restrict__ t, int64_t pitch, int W, int r0, int n, int a,
@@ -81,7 +135,12 @@ __device__ __forceinline__ void chamfer_rows(float* __restrict__ t, int64_t pitc
 }
 
 __global__ void __launch_bounds__(64) chamfer_cols_kernel(const uint8_t* x, int64_t pitch, float* t, int H, int W) {
-  chamfer_cols(x, pitch, t, H, W, blockIdx.x * 64);
+  __shared__ uint32_t sbits[CH_WORDS * 64];
+  __shared__ int32_t snext[CH_WORDS * 64];
+  if (H <= 32 * CH_WORDS)
+    chamfer_cols_bits(x, pitch, t, H, W, blockIdx.x * 64, sbits, snext);
+  else
+    chamfer_cols(x, pitch, t, H, W, blockIdx.x * 64);
 }
 
 __global__ void __launch_bounds__(CH_ROWS_NT) chamfer_rows_kernel(float* t, int64_t pitch, int H, int W, int a,
@@ -94,10 +153,15 @@ __global__ void __launch_bounds__(CH_ROWS_NT) chamfer_rows_kernel(float* t, int6
 __global__ void __launch_bounds__(64) chamfer_cols_batched_kernel(const ImageDesc* __restrict__ images,
                                                                   const ChamferTask* __restrict__ tasks, int ntasks,
                                                                   const uint8_t* x, float* t) {
+  __shared__ uint32_t sbits[CH_WORDS * 64];
+  __shared__ int32_t snext[CH_WORDS * 64];
   for (int k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const ChamferTask c = tasks[k];
     const ImageDesc im = images[c.img];
-    chamfer_cols(x + im.weight_off, im.pitch, t + im.weight_off, im.H, im.W, c.pos * 64);
+    if (im.H <= 32 * CH_WORDS)
+      chamfer_cols_bits(x + im.weight_off, im.pitch, t + im.weight_off, im.H, im.W, c.pos * 64, sbits, snext);
+    else
+      chamfer_cols(x + im.weight_off, im.pitch, t + im.weight_off, im.H, im.W, c.pos * 64);
   }
 }
 

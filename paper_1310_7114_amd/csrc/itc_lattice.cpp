@@ -562,8 +562,8 @@ itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t
   itc_status st = check_chamfer_mask(a, b);
   if (st != ITC_OK) return st;
   const int cus = device_cus();
-  const int gc = std::min((int)p->ch_cols.size(), 16 * cus);
-  const int gr = std::min((int)p->ch_rows.size(), 4 * cus);
+  const int gc = std::min((int)p->ch_cols.size(), 64 * cus);
+  const int gr = std::min((int)p->ch_rows.size(), 8 * cus);
   hipError_t e = itc::launch_chamfer_batched(p->d_images, p->d_ch_cols, (int)p->ch_cols.size(), p->d_ch_rows,
                                              (int)p->ch_rows.size(), p->w_max, weights, t_out, a, b, gc, gr,
                                              (hipStream_t)stream);

@@ -39,6 +39,10 @@ CASES = [
     ("all_fg_70x129", lambda: np.ones((70, 129), np.uint8)),
     ("all_bg_40x40", lambda: np.zeros((40, 40), np.uint8)),
     ("gray_levels", lambda: S.gray_gaussians((7, 2), H=90, W=140, n=6, major=(10, 30))),
+    # columns of at most 1,024 rows take the bit-mask column pass, taller ones the two-walk pass
+    ("rows1024", lambda: rand_img(8, 1024, 70, 0.995)),
+    ("rows1025", lambda: rand_img(9, 1025, 70, 0.995)),
+    ("tall1500x33", lambda: rand_img(10, 1500, 33, 0.99)),
 ]
 
 
