@@ -70,6 +70,7 @@ typedef enum { ITC_U8 = 0, ITC_F32 = 1, ITC_F64 = 2 } itc_dtype;
 #define ITC_MAX_CODEVECTORS 1024
 #define ITC_MAX_CHAMFER_WIDTH 16384 /* widest image the chamfer transform accepts */
 #define ITC_MAX_CHAMFER_STEP 64     /* largest orthogonal step cost of the chamfer mask */
+#define ITC_MAX_LITERAL_RADIUS 256  /* largest window radius of G_omega in Algorithm 1 */
 
 /*
  * One lattice problem. The weight image (Section 3.2 binary image, or
@@ -180,6 +181,39 @@ itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void
  */
 itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t a, int32_t b,
                                float* t_out, void* stream);
+
+/*
+ * Algorithm 1 as the paper states it, with the update eq. (6): P = X * G_xi
+ * once; then per sweep Q = W * G_omega with the codebook as an image of M
+ * impulses, V(X;W) = sum P Q and V(W) = sum Q^2 over the lattice, and for
+ * every codevector eq. (6) with G_omega(x - w_k) replaced by its sampled mask
+ * F over the window |x - w_k| <= R_omega (Section 3.1). Codevectors are
+ * lattice points: the value eq. (6) gives is rounded to the nearest lattice
+ * point (halves upward) and clamped into the lattice. A codevector with
+ * sum P F = 0 keeps its place; sweeps are Jacobi.
+ *   d            the weight image and P's width: sigma = xi, radius = R_xi
+ *                (0: ceil(3 xi)); real_dtype must be ITC_F32;
+ *   weights      device weight image as in itc_lattice_precompute;
+ *   omega        width of Q and F (> 0); radius_omega: R_omega (0: ceil(3 omega),
+ *                at most ITC_MAX_LITERAL_RADIUS);
+ *   w_init       device int32 [M][2] lattice points (u, v) (clamped into the
+ *                lattice); w_out: device int32 [M][2] (may alias w_init);
+ *   iters        sweeps (>= 0); theta: stop once no codevector moved farther
+ *                than theta (< 0: run all sweeps);
+ *   d_trace      device double [iters + 1] or NULL: D = log V(W) + log V(X)
+ *                - 2 log V(X;W) before each sweep and after the last;
+ *   iters_done   device int32 or NULL;
+ *   work         device scratch of itc_lattice_literal_work_bytes(d, M,
+ *                omega, radius_omega) bytes, 256-byte aligned (overwritten).
+ * The paper's experiments choose omega = sqrt(N/M)/2 and xi = omega/2.
+ * Asynchronous on `stream`: 2 (iters + 2) launches, no allocation.
+ */
+size_t itc_lattice_literal_work_bytes(const itc_lattice_desc* d, int32_t M, double omega,
+                                      int32_t radius_omega);
+itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weights, double omega,
+                                   int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                   double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,
+                                   void* work, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: n independent images of uneven size, each with its own M,

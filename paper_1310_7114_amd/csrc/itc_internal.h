@@ -108,6 +108,25 @@ struct SxBlock {
   int32_t img;
   int32_t b;
 };
+// Algorithm 1 (eq. (6) on the lattice): device pointers into the caller's
+// work buffer and the sweep parameters.
+struct LiteralArgs {
+  const float* P;   // A plane of the maps with sigma = xi
+  int64_t ppitch;   // elements per P row
+  int32_t H, W, M;
+  int32_t R;        // window radius of G_omega
+  int32_t iters;
+  int32_t nvx;      // row blocks of the V(X) sum
+  double omega, theta;
+  double* taps;     // [R + 1] g, then [2R + 1] window overlaps
+  double* vx_part;  // [nvx]
+  double* terms;    // [6 M]: a, b_u, b_v, e, d_u, d_v
+  int32_t* state;
+  double* d_trace;      // [iters + 1] or null
+  int32_t* iters_done;  // or null
+};
+hipError_t launch_literal(const LiteralArgs& la, const int32_t* w_init, int32_t* w_out, hipStream_t s);
+
 // Chamfer transform: a task is (image, strip) for the column pass and
 // (image, first row) for the row pass.
 struct ChamferTask {

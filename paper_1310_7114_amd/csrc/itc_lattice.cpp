@@ -524,6 +524,85 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
   return ok();
 }
 
+// Algorithm 1: the work buffer holds the maps of P, then the taps and window
+// overlaps, the V(X) row-block sums, the per-codevector sums and the state.
+struct LiteralLayout {
+  size_t maps, taps, vx, terms, state, total;
+  int R, nvx;
+};
+
+static bool literal_layout(const itc_lattice_desc& d, int32_t M, double omega, int32_t radius_omega,
+                           LiteralLayout& L) {
+  if (!(omega > 0.0) || !std::isfinite(omega)) return false;
+  const double rr = std::ceil(3.0 * omega - 1e-12);
+  const int R = radius_omega > 0 ? radius_omega : (rr > ITC_MAX_LITERAL_RADIUS ? ITC_MAX_LITERAL_RADIUS + 1 : (int)rr);
+  if (R < 1 || R > ITC_MAX_LITERAL_RADIUS || M < 1) return false;
+  L.R = R;
+  L.nvx = (d.height + 15) / 16;
+  L.maps = 0;
+  L.taps = (maps_bytes_of(d) + 255) / 256 * 256;
+  L.vx = L.taps + (size_t)(3 * R + 2) * sizeof(double);
+  L.terms = L.vx + (size_t)L.nvx * sizeof(double);
+  L.state = L.terms + (size_t)6 * M * sizeof(double);
+  L.total = (L.state + 8 + 255) / 256 * 256;
+  return true;
+}
+
+size_t itc_lattice_literal_work_bytes(const itc_lattice_desc* d, int32_t M, double omega, int32_t radius_omega) {
+  int R = 0, rc = 0;
+  if (!d || check_desc(d, &R, &rc) != ITC_OK) return 0;
+  LiteralLayout L;
+  if (!literal_layout(*d, M, omega, radius_omega, L)) return 0;
+  return L.total;
+}
+
+itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weights, double omega,
+                                   int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                   double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
+                                   void* stream) {
+  int R = 0, rc = 0;
+  itc_status st = check_desc(d, &R, &rc);
+  if (st != ITC_OK) return st;
+  if (!weights || !w_init || !w_out || !work) return fail(ITC_E_NULL, "weights, w_init, w_out and work must be non-NULL");
+  if (d->real_dtype != ITC_F32) return fail(ITC_E_UNSUPPORTED, "Algorithm 1 runs with real_dtype ITC_F32");
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ITC_E_ARG, "omega must be finite and > 0 (got %g)", omega);
+  if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
+  if (M > ITC_MAX_CODEVECTORS) return fail(ITC_E_UNSUPPORTED, "M %d exceeds %d", M, ITC_MAX_CODEVECTORS);
+  if (iters < 0) return fail(ITC_E_ARG, "iters must be >= 0 (got %d)", iters);
+  if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
+  if (!aligned256(work)) return fail(ITC_E_ARG, "work must be 256-byte aligned");
+  LiteralLayout L;
+  if (!literal_layout(*d, M, omega, radius_omega, L))
+    return fail(radius_omega < 0 ? ITC_E_ARG : ITC_E_UNSUPPORTED, "omega window radius must be 1..%d",
+                ITC_MAX_LITERAL_RADIUS);
+  ImageDesc im = make_image(*d, R, rc);
+  hipStream_t s = (hipStream_t)stream;
+  char* wb = (char*)work;
+  hipError_t e = itc::launch_conv_image(false, im, weights, wb + L.maps, s);
+  if (e != hipSuccess) return device_fail(e, "convolution launch");
+  itc::LiteralArgs la;
+  std::memset(&la, 0, sizeof la);
+  la.P = reinterpret_cast<const float*>(wb + L.maps);
+  la.ppitch = im.map_pitch;
+  la.H = d->height;
+  la.W = d->width;
+  la.M = M;
+  la.R = L.R;
+  la.iters = iters;
+  la.nvx = L.nvx;
+  la.omega = omega;
+  la.theta = theta;
+  la.taps = reinterpret_cast<double*>(wb + L.taps);
+  la.vx_part = reinterpret_cast<double*>(wb + L.vx);
+  la.terms = reinterpret_cast<double*>(wb + L.terms);
+  la.state = reinterpret_cast<int32_t*>(wb + L.state);
+  la.d_trace = d_trace;
+  la.iters_done = iters_done;
+  e = itc::launch_literal(la, w_init, w_out, s);
+  if (e != hipSuccess) return device_fail(e, "Algorithm 1 launch");
+  return ok();
+}
+
 static itc_status check_chamfer_mask(int32_t a, int32_t b) {
   if (a < 1 || a > ITC_MAX_CHAMFER_STEP || b < a || b > 2 * a)
     return fail(ITC_E_ARG, "chamfer steps need 1 <= a <= b <= 2a and a <= %d (got a=%d, b=%d)",

@@ -64,6 +64,9 @@ SIGNATURES = {
     "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_divergence_backward_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer": (ctypes.c_int, [_DP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "itc_lattice_literal_work_bytes": (ctypes.c_size_t, [_DP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
+    "itc_lattice_literal_fit": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P,
+                                               ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_destroy": (None, [_P]),
@@ -218,6 +221,39 @@ def chamfer(x: torch.Tensor, a: int = 3, b: int = 4, out: Optional[torch.Tensor]
         out = torch.empty((H, x.stride(0)), dtype=torch.float32, device=x.device)
     _check(load().itc_lattice_chamfer(ctypes.byref(desc), _ptr(x), int(a), int(b), _ptr(out), _stream()))
     return out[:, :W]
+
+
+def paper_widths(N: float, M: int):
+    """(xi, omega) of the paper's runtime experiments: omega = sqrt(N/M)/2, xi = omega/2."""
+    omega = (float(N) / M) ** 0.5 / 2.0
+    return omega / 2.0, omega
+
+
+def fit_literal(weights: torch.Tensor, w_init: torch.Tensor, xi: float, omega: float, iters: int,
+                theta: float = -1.0, scale: float = 1.0, radius_xi: int = 0, radius_omega: int = 0,
+                trace: bool = True, work: Optional[torch.Tensor] = None):
+    """Algorithm 1 with eq. (6) on the lattice. w_init: (M, 2) int32 lattice points (u, v).
+    Returns (W int32 (M, 2), D trace or None, sweeps done tensor)."""
+    if weights.dim() != 2:
+        raise ValueError("weights must be (H, W)")
+    if weights.stride(1) != 1:
+        weights = weights.contiguous()
+    H, W = weights.shape
+    desc = make_desc(H, W, xi, weights.dtype, torch.float32, scale, radius_xi, pitch=weights.stride(0))
+    w_init = w_init.to(torch.int32).contiguous()
+    M = int(w_init.shape[0])
+    nb = load().itc_lattice_literal_work_bytes(ctypes.byref(desc), M, float(omega), int(radius_omega))
+    if nb == 0:
+        raise ItcError(2, "invalid Algorithm 1 parameters: " + load().itc_last_error().decode())
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=weights.device)
+    w_out = torch.empty_like(w_init)
+    d_trace = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=weights.device) if trace else None
+    done = torch.zeros(1, dtype=torch.int32, device=weights.device)
+    _check(load().itc_lattice_literal_fit(ctypes.byref(desc), _ptr(weights), float(omega), int(radius_omega), M,
+                                          _ptr(w_init), int(iters), float(theta), _ptr(w_out), _ptr(d_trace),
+                                          _ptr(done), _ptr(work), _stream()))
+    return w_out, d_trace, done
 
 
 # ---------------------------------------------------------------------------

@@ -125,6 +125,32 @@ def test_chamfer_arguments(itc):
     assert lib.itc_lattice_chamfer_batched(None, P, 3, 4, P, None) == 1
 
 
+def test_literal_arguments(itc):
+    import torch
+    lib = itc.load()
+    P = ctypes.c_void_p(256)
+    d = itc.make_desc(64, 70, 2.5)
+    wb = lib.itc_lattice_literal_work_bytes
+    n = wb(ctypes.byref(d), 16, 5.0, 0)
+    assert n > 0 and n % 256 == 0 and n >= itc.maps_bytes(d)
+    assert wb(ctypes.byref(d), 16, 0.0, 0) == 0           # omega must be > 0
+    assert wb(ctypes.byref(d), 16, 100.0, 0) == 0         # ceil(3 omega) beyond ITC_MAX_LITERAL_RADIUS
+    assert wb(ctypes.byref(d), 16, 2.0, 257) == 0
+    assert wb(ctypes.byref(d), 0, 2.0, 0) == 0
+    assert wb(None, 16, 2.0, 0) == 0
+    fit = lib.itc_lattice_literal_fit
+    assert fit(ctypes.byref(d), None, 5.0, 0, 16, P, 10, -1.0, P, None, None, P, None) == 1
+    assert fit(ctypes.byref(d), P, 5.0, 0, 16, P, 10, -1.0, P, None, None, None, None) == 1
+    assert fit(ctypes.byref(d), P, -1.0, 0, 16, P, 10, -1.0, P, None, None, P, None) == 2
+    assert fit(ctypes.byref(d), P, 5.0, 0, 0, P, 10, -1.0, P, None, None, P, None) == 2
+    assert fit(ctypes.byref(d), P, 5.0, 0, 16, P, -1, -1.0, P, None, None, P, None) == 2
+    assert fit(ctypes.byref(d), P, 5.0, 0, 16, P, 10, float("nan"), P, None, None, P, None) == 2
+    assert fit(ctypes.byref(d), P, 5.0, 0, 16, P, 10, -1.0, P, None, None, ctypes.c_void_p(264), None) == 2
+    assert fit(ctypes.byref(d), P, 5.0, 300, 16, P, 10, -1.0, P, None, None, P, None) == 3
+    d64 = itc.make_desc(64, 70, 2.5, real_dtype=torch.float64)
+    assert fit(ctypes.byref(d64), P, 5.0, 0, 16, P, 10, -1.0, P, None, None, P, None) == 3
+
+
 def test_plan_rejects_bad_batches(itc):
     lib = itc.load()
     h = ctypes.c_void_p()

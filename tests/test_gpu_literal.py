@@ -1,0 +1,127 @@
+"""Algorithm 1 with eq. (6) on the lattice: the HIP path against the oracle.
+
+Codevectors are lattice points, so every sweep ends in a rounding decision.
+The GPU computes P in FP32 (the convolution maps) and everything after in
+FP64; the oracle is FP64 throughout, so a continuous update that lands within
+about 1e-5 px of a half-integer can round the other way. The trajectories are
+compared sweep by sweep: they must agree until the first codebook
+difference, and that difference must sit on such a near-tie of the oracle's
+continuous update (then the two runs are both correct and diverge). D agrees
+to 1e-6 relative while the codebooks agree.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1310_7114_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+TIE = 1e-3  # px: a rounding decision this close to a half-integer may go either way
+
+
+def gpu_run(itc, case, xi, omega, iters, theta=-1.0, w0=None):
+    x = torch.from_numpy(case.img).cuda()
+    w0 = case.w0 if w0 is None else w0
+    w, tr, done = itc.fit_literal(x, torch.from_numpy(np.asarray(w0)).cuda().to(torch.int32), xi, omega, iters,
+                                  theta=theta, scale=case.scale)
+    torch.cuda.synchronize()
+    return w.cpu().numpy().astype(np.float64), tr.cpu().numpy(), int(done.cpu()[0])
+
+
+def oracle_trajectory(case, xi, omega, T):
+    Rx = int(math.ceil(3 * xi - 1e-12))
+    Ro = int(math.ceil(3 * omega - 1e-12))
+    P = O.density_map(case.weights, xi, Rx)
+    W = np.array(case.w0, np.float64)
+    Ws, raw, D = [W], [], [O.literal_divergence(P, W, omega, Ro)]
+    H, Wd = case.img.shape
+    for _ in range(T):
+        wn, _, _, _ = O.literal_step(P, W, omega, Ro)
+        raw.append(wn)
+        r = np.floor(wn + 0.5)
+        r[:, 0] = np.clip(r[:, 0], 0, H - 1)
+        r[:, 1] = np.clip(r[:, 1], 0, Wd - 1)
+        W = r
+        Ws.append(W)
+        D.append(O.literal_divergence(P, W, omega, Ro))
+    return Ws, raw, np.array(D)
+
+
+def compare(itc, case, xi, omega, T):
+    Ws, raw, D = oracle_trajectory(case, xi, omega, T)
+    _, trace, _ = gpu_run(itc, case, xi, omega, T)
+    agreed = 0
+    for t in range(1, T + 1):
+        w, tr, done = gpu_run(itc, case, xi, omega, t)
+        assert done == t
+        if np.array_equal(w, Ws[t]):
+            agreed = t
+            continue
+        # the first difference must be a near-tie of the oracle's continuous update
+        bad = np.argwhere(w != Ws[t])
+        for k, ax in bad:
+            frac = raw[t - 1][k, ax] - np.floor(raw[t - 1][k, ax])
+            assert abs(frac - 0.5) < TIE, (t, k, ax, raw[t - 1][k, ax], w[k, ax])
+            assert abs(w[k, ax] - Ws[t][k, ax]) == 1.0
+        break
+    # D of every codebook the two runs share
+    n = agreed + 1
+    assert np.allclose(trace[:n], D[:n], rtol=1e-6, atol=0)
+    return agreed
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_literal_config1(gpu_lib, seed):
+    """64 x 64 ellipses, M = 16, the paper's widths omega = sqrt(N/M)/2, xi = omega/2."""
+    case = S.config1_case(seed)
+    xi, om = O.paper_widths(float(case.img.sum()), case.M)
+    agreed = compare(gpu_lib, case, xi, om, 20)
+    assert agreed >= 10
+
+
+def test_literal_config2(gpu_lib):
+    """512 x 512 shapes, M = 100, paper widths (xi = 6.6, omega = 13.2: windows of 81 x 81 pixels)."""
+    case = S.config2_case(0)
+    xi, om = O.paper_widths(float(case.img.sum()), case.M)
+    agreed = compare(gpu_lib, case, xi, om, 12)
+    assert agreed >= 6
+
+
+def test_literal_equal_widths_and_theta(gpu_lib):
+    """xi = omega = 2 (R = 6) to convergence: theta = 0.5 stops once no codevector moves."""
+    case = S.config1_case(1)
+    w, tr, done = gpu_run(gpu_lib, case, 2.0, 2.0, 100, theta=0.5)
+    Wo, tro, doneo, _ = O.fit_literal(case.weights, case.w0, 2.0, 2.0, 100, theta=0.5)
+    assert done < 100
+    if np.array_equal(w, Wo):
+        assert done == doneo
+        assert np.allclose(tr[:done + 1], tro, rtol=1e-6)
+    # converged on the lattice: one more sweep moves nothing
+    w2, _, _ = gpu_run(gpu_lib, case, 2.0, 2.0, 1, w0=w.astype(np.int32))
+    assert np.array_equal(w2, w)
+
+
+def test_literal_zero_sweeps_and_clamp(gpu_lib):
+    case = S.config1_case(2)
+    xi, om = O.paper_widths(float(case.img.sum()), case.M)
+    w, tr, done = gpu_run(gpu_lib, case, xi, om, 0)
+    assert done == 0 and np.array_equal(w, case.w0)
+    P = O.density_map(case.weights, xi, int(math.ceil(3 * xi - 1e-12)))
+    assert tr[0] == pytest.approx(O.literal_divergence(P, case.w0, om, int(math.ceil(3 * om - 1e-12))), rel=1e-6)
+    w0 = case.w0.astype(np.int32).copy()
+    w0[0] = (-5, 3)
+    w0[1] = (70, 200)
+    w, _, _ = gpu_run(gpu_lib, case, xi, om, 0, w0=w0)
+    assert tuple(w[0]) == (0, 3) and tuple(w[1]) == (63, 63)
+
+
+def test_literal_rejects_bad_arguments(gpu_lib):
+    x = torch.ones((8, 8), dtype=torch.uint8, device="cuda")
+    w0 = torch.zeros((2, 2), dtype=torch.int32, device="cuda")
+    for om, r in ((0.0, 0), (float("nan"), 0), (100.0, 0), (2.0, 257)):
+        with pytest.raises(gpu_lib.ItcError):
+            gpu_lib.fit_literal(x, w0, 1.0, om, 3, radius_omega=r)
