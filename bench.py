@@ -68,6 +68,11 @@ def _oracle_fit(args):
     return 1
 
 
+def synth_config2():
+    from paper_1310_7114_amd import synth
+    return synth.config2_case(0)
+
+
 def cpu_legs(cases, seconds):
     """The FP64 oracle on the host cores, run before the GPU is touched: the
     lattice variant on one core (the reported baseline) and on every core of
@@ -142,6 +147,15 @@ def cpu_legs(cases, seconds):
         "original_s_per_sweep": t_orig / max(done, 1), "lattice_s_per_sweep": t_lat / max(done, 1),
         "ratio": t_orig / t_lat if t_lat > 0 else None,
         "original_images_per_s_extrapolated_100_sweeps": done / (100.0 * t_orig) if t_orig > 0 else None}
+    # Algorithm 1 (eq. (6) on the lattice): one oracle sweep on the 512 x 512
+    # shapes with the paper's widths
+    c2 = synth_config2()
+    xi2, om2 = O.paper_widths(float(c2.img.sum()), c2.M)
+    P2 = O.density_map(c2.weights, xi2, int(np.ceil(3 * xi2 - 1e-12)))
+    t = time.perf_counter()
+    O.literal_step(P2, c2.w0, om2, int(np.ceil(3 * om2 - 1e-12)))
+    ctx["literal_shapes512_sweep_s"] = time.perf_counter() - t
+
     # Section 5: the oracle's two-pass chamfer transform on the first silhouettes
     t = time.perf_counter()
     k3, px3 = 0, 0
@@ -256,6 +270,19 @@ def gpu_extras(dev, cases, itc, synth):
                                   "weighted_fit_ms": t_wrun * 1e3,
                                   "weighted_images_per_s": len(cases) / (t_ch + t_wrun)}
     del pu8, pw, tch
+
+    # Algorithm 1 as printed (eq. (6), lattice codevectors) on the 512 x 512
+    # shapes with the paper's widths: time per sweep (the paper's Fig. 4 metric)
+    c2 = synth.config2_case(0)
+    xi2, om2 = itc.paper_widths(float(c2.img.sum()), c2.M)
+    x2 = torch.from_numpy(c2.img).to(dev)
+    w02 = torch.from_numpy(c2.w0).to(dev).to(torch.int32)
+    work = torch.empty(1 << 26, dtype=torch.uint8, device=dev)
+    t20 = timed(lambda: itc.fit_literal(x2, w02, xi2, om2, 20, work=work), reps=3)
+    t0 = timed(lambda: itc.fit_literal(x2, w02, xi2, om2, 0, work=work), reps=3)
+    out["literal_shapes512"] = {"xi": xi2, "omega": om2, "M": c2.M, "sweeps": 20, "ms_total": t20 * 1e3,
+                                "ms_per_sweep": (t20 - t0) / 20 * 1e3, "ms_setup": t0 * 1e3}
+    del work
 
     c5 = synth.config5_cases(64)
     p = itc.BatchPlan([torch.from_numpy(c.img) for c in c5], [c.M for c in c5], [c.sigma for c in c5],
