@@ -269,7 +269,15 @@ def gpu_extras(dev, cases, itc, synth):
                                   "gbs_algorithmic": 5.0 * npx_all / t_ch / 1e9, "bytes_per_px": 5,
                                   "weighted_fit_ms": t_wrun * 1e3,
                                   "weighted_images_per_s": len(cases) / (t_ch + t_wrun)}
-    del pu8, pw, tch
+    # segments of every silhouette for its fitted codebook (nearest codevector per pixel)
+    w0s = pu8.pack_codebooks([c.w0 for c in cases], device=dev)
+    wfit = torch.empty_like(w0s)
+    pu8.run(w0s, wfit)
+    lab = pu8.label(wfit)
+    t_lab = timed(lambda: pu8.label(wfit, out=lab))
+    out["segments_silhouettes"] = {"images": len(cases), "pixels": int(npx_all), "ms": t_lab * 1e3,
+                                   "gpx_per_s": npx_all / t_lab / 1e9}
+    del pu8, pw, tch, lab
 
     # Algorithm 1 as printed (eq. (6), lattice codevectors) on the 512 x 512
     # shapes with the paper's widths: time per sweep (the paper's Fig. 4 metric)

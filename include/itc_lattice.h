@@ -215,6 +215,21 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
                                    double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,
                                    void* work, void* stream);
 
+/*
+ * Segments of a codebook (the shape segments of Section 4): labels(x) is the
+ * index of the codevector nearest to pixel x (Euclidean; the smaller index on
+ * equal distances) for every pixel of weight h(x) = weight_scale * stored > 0,
+ * and -1 elsewhere. Distances are (u - w_u)^2 + (v - w_v)^2 in FP64 with two
+ * rounded products and a rounded sum.
+ *   d        weight image layout (sigma and radius are validated but unused);
+ *   weights  device, as in itc_lattice_precompute;
+ *   w        device [M][2] codebook in the real type;
+ *   labels   device int32, height x pitch (written at the image's pitch).
+ * Asynchronous on `stream`; no allocation.
+ */
+itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,
+                             int32_t* labels, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: n independent images of uneven size, each with its own M,
  * sigma and iteration count, in flat device buffers. A plan is built once per
@@ -278,6 +293,14 @@ itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps
  */
 itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t a, int32_t b, float* t_out,
                                        void* stream);
+
+/*
+ * Segments (itc_lattice_label) of every image of a plan with its codebook
+ * from `w` (the w_init layout, FP32). Image i's labels are written at int32
+ * offset weight_off[i] / sizeof(stored weight) of `labels`, at its pitch.
+ */
+itc_status itc_lattice_label_batched(itc_plan* p, const void* weights, const void* w, int32_t* labels,
+                                     void* stream);
 
 /* Number of images in the plan, or -1 for NULL. */
 int32_t itc_lattice_plan_size(const itc_plan* p);

@@ -8,9 +8,10 @@ imports nothing from the product.
 Readings (listed with the design notes): a pixel with weight > 0 belongs to
 the codevector nearest to it in the Euclidean norm (the Voronoi cell of the
 codebook, as in vector quantisation); equal distances go to the smaller
-index; pixels of weight 0 get -1. Distances are evaluated in FP64, where
-(u - w_u)^2 + (v - w_v)^2 is exact for FP32 codebook coordinates and lattice
-pixels, so the decision does not depend on rounding.
+index; pixels of weight 0 get -1. Distances are (u - w_u)^2 + (v - w_v)^2 in
+FP64 with two rounded products and a rounded sum (exact whenever the
+coordinates stay below 2048 and the codebook is FP32), the order the GPU
+kernel uses too, so both sides take the same decisions.
 """
 from __future__ import annotations
 

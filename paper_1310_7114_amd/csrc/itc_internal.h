@@ -138,6 +138,11 @@ hipError_t launch_chamfer(const ImageDesc& im, const void* x, float* t, int a, i
 hipError_t launch_chamfer_batched(const ImageDesc* d_images, const ChamferTask* d_cols, int ncols,
                                   const ChamferTask* d_rows, int nrows, int w_max, const void* x, float* t, int a,
                                   int b, int grid_cols, int grid_rows, hipStream_t s);
+int label_rows_per_task();
+hipError_t launch_label(bool f64, const ImageDesc& im, const void* x, const void* w, int M, int32_t* lab,
+                        hipStream_t s);
+hipError_t launch_label_batched(const ImageDesc* d_images, const ChamferTask* d_tasks, int ntasks, int m_max,
+                                const void* x, const void* w, int32_t* lab, int grid, hipStream_t s);
 hipError_t launch_sx_blocks_batched(bool f64, const ImageDesc* d_images, const SxBlock* d_blocks, int nblocks,
                                     void* maps, int grid, hipStream_t s);
 

@@ -375,6 +375,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     p->all_u8 = p->all_u8 && im.wdtype == ITC_U8;
     p->w_max = std::max(p->w_max, im.W);
     for (int st2 = 0; st2 < im.nstrips; ++st2) p->ch_cols.push_back(itc::ChamferTask{i, st2});
+    // row groups shared by the chamfer row pass and the labelling (equal heights, checked below)
     for (int r0 = 0; r0 < im.H; r0 += itc::chamfer_rows_per_task()) p->ch_rows.push_back(itc::ChamferTask{i, r0});
   }
   for (int rc = 0; rc < NKEYS; ++rc) {
@@ -600,6 +601,33 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
   la.iters_done = iters_done;
   e = itc::launch_literal(la, w_init, w_out, s);
   if (e != hipSuccess) return device_fail(e, "Algorithm 1 launch");
+  return ok();
+}
+
+itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,
+                             int32_t* labels, void* stream) {
+  int R = 0, rc = 0;
+  itc_status st = check_desc(d, &R, &rc);
+  if (st != ITC_OK) return st;
+  if (!weights || !w || !labels) return fail(ITC_E_NULL, "weights, w and labels must be non-NULL");
+  if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
+  if (M > ITC_MAX_CODEVECTORS) return fail(ITC_E_UNSUPPORTED, "M %d exceeds %d", M, ITC_MAX_CODEVECTORS);
+  ImageDesc im = make_image(*d, R, rc);
+  hipError_t e = itc::launch_label(d->real_dtype == ITC_F64, im, weights, w, M, labels, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "labelling launch");
+  return ok();
+}
+
+itc_status itc_lattice_label_batched(itc_plan* p, const void* weights, const void* w, int32_t* labels,
+                                     void* stream) {
+  if (!p || !weights || !w || !labels) return fail(ITC_E_NULL, "plan, weights, w and labels must be non-NULL");
+  if (itc::label_rows_per_task() != itc::chamfer_rows_per_task())
+    return fail(ITC_E_DEVICE, "row groups of the labelling and the chamfer pass differ");
+  const int cus = device_cus();
+  const int grid = std::min((int)p->ch_rows.size(), 8 * cus);
+  hipError_t e = itc::launch_label_batched(p->d_images, p->d_ch_rows, (int)p->ch_rows.size(), p->m_max, weights, w,
+                                           labels, grid, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "batched labelling launch");
   return ok();
 }
 

@@ -64,6 +64,8 @@ SIGNATURES = {
     "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_divergence_backward_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer": (ctypes.c_int, [_DP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "itc_lattice_label": (ctypes.c_int, [_DP, _P, ctypes.c_int32, _P, _P, _P]),
+    "itc_lattice_label_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "itc_lattice_literal_work_bytes": (ctypes.c_size_t, [_DP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
     "itc_lattice_literal_fit": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P,
                                                ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
@@ -223,6 +225,23 @@ def chamfer(x: torch.Tensor, a: int = 3, b: int = 4, out: Optional[torch.Tensor]
     return out[:, :W]
 
 
+def label(weights: torch.Tensor, w: torch.Tensor, scale: float = 1.0, out: Optional[torch.Tensor] = None,
+          real_dtype=torch.float32) -> torch.Tensor:
+    """Segments: int32 (H, W) index of the nearest codevector for pixels of weight > 0, -1 elsewhere."""
+    if weights.dim() != 2:
+        raise ValueError("weights must be (H, W)")
+    if weights.stride(1) != 1:
+        weights = weights.contiguous()
+    H, W = weights.shape
+    desc = make_desc(H, W, 1.0, weights.dtype, real_dtype, scale, 0, pitch=weights.stride(0))
+    w = w.to(real_dtype).contiguous()
+    if out is None:
+        out = torch.empty((H, weights.stride(0)), dtype=torch.int32, device=weights.device)
+    _check(load().itc_lattice_label(ctypes.byref(desc), _ptr(weights), int(w.shape[0]), _ptr(w), _ptr(out),
+                                    _stream()))
+    return out[:, :W]
+
+
 def paper_widths(N: float, M: int):
     """(xi, omega) of the paper's runtime experiments: omega = sqrt(N/M)/2, xi = omega/2."""
     omega = (float(N) / M) ** 0.5 / 2.0
@@ -335,6 +354,15 @@ class BatchPlan:
         if out is None:
             out = torch.empty(w.numel(), dtype=torch.float32, device=w.device)
         _check(load().itc_lattice_chamfer_batched(self.handle, _ptr(w), int(a), int(b), _ptr(out), _stream()))
+        return out
+
+    def label(self, w: torch.Tensor, weights=None, out=None) -> torch.Tensor:
+        """Segments of every image for the packed FP32 codebooks `w`: an int32 buffer holding image i
+        at element offset weight_off[i] / element size, at the images' pitch."""
+        x = self._w(weights)
+        if out is None:
+            out = torch.empty(x.numel(), dtype=torch.int32, device=x.device)
+        _check(load().itc_lattice_label_batched(self.handle, _ptr(x), _ptr(w), _ptr(out), _stream()))
         return out
 
     def weighted(self, a: int = 3) -> "BatchPlan":

@@ -151,6 +151,18 @@ def test_literal_arguments(itc):
     assert fit(ctypes.byref(d64), P, 5.0, 0, 16, P, 10, -1.0, P, None, None, P, None) == 3
 
 
+def test_label_arguments(itc):
+    lib = itc.load()
+    P = ctypes.c_void_p(256)
+    d = itc.make_desc(16, 16, 1.0)
+    assert lib.itc_lattice_label(ctypes.byref(d), None, 4, P, P, None) == 1
+    assert lib.itc_lattice_label(ctypes.byref(d), P, 4, None, P, None) == 1
+    assert lib.itc_lattice_label(ctypes.byref(d), P, 4, P, None, None) == 1
+    assert lib.itc_lattice_label(ctypes.byref(d), P, 0, P, P, None) == 2
+    assert lib.itc_lattice_label(ctypes.byref(d), P, 1025, P, P, None) == 3
+    assert lib.itc_lattice_label_batched(None, P, P, P, None) == 1
+
+
 def test_plan_rejects_bad_batches(itc):
     lib = itc.load()
     h = ctypes.c_void_p()
