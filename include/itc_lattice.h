@@ -230,6 +230,26 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
 itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,
                              int32_t* labels, void* stream);
 
+/*
+ * Maps for large widths by recursive filtering (Section 3.1: for large kernel
+ * widths recursive filters replace the finite masks; Deriche and van Vliet are
+ * cited). Writes the same maps layout and S_X as itc_lattice_precompute, with
+ * the Gaussian of width sigma replaced by Young and van Vliet's third-order
+ * recursive Gaussian along v, then u (scaled to the mass of the unnormalised
+ * sampled Gaussian), on the lattice grown by a one-pixel ring of zero weights
+ * with every line extended by ceil(6 sigma) zeros; M = -sigma^2 grad A by
+ * central differences. Cost per pixel independent of sigma; radius unused.
+ * Map columns >= width are written as 0. Requires sigma >= 0.5 and
+ * real_dtype ITC_F32. `maps` at itc_lattice_recursive_maps_bytes(d) bytes and
+ * `work` at itc_lattice_recursive_work_bytes(d) bytes, both device and
+ * 256-byte aligned; `s_x` one device double. itc_lattice_fit and
+ * itc_lattice_divergence accept these maps for any sigma.
+ */
+size_t itc_lattice_recursive_maps_bytes(const itc_lattice_desc* d);
+size_t itc_lattice_recursive_work_bytes(const itc_lattice_desc* d);
+itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const void* weights, void* maps,
+                                            double* s_x, void* work, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: n independent images of uneven size, each with its own M,
  * sigma and iteration count, in flat device buffers. A plan is built once per

@@ -108,6 +108,15 @@ struct SxBlock {
   int32_t img;
   int32_t b;
 };
+// Young-van Vliet recursive Gaussian: coefficients, output gain and the
+// zero margin appended to every line.
+struct RecCoeffs {
+  double B, a1, a2, a3, gain;
+  int m;
+};
+hipError_t launch_recursive(const ImageDesc& im, const void* x, double scale, double sigma, const RecCoeffs& rc,
+                            double* E1, double* E2, void* maps, hipStream_t s);
+
 // Algorithm 1 (eq. (6) on the lattice): device pointers into the caller's
 // work buffer and the sweep parameters.
 struct LiteralArgs {

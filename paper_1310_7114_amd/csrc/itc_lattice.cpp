@@ -49,7 +49,10 @@ int effective_radius(const itc_lattice_desc& d) {
 }
 
 // Validates a descriptor; on success fills R and its compiled radius class.
-itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out) {
+// need_class: the entry point runs the mask convolution, so the window
+// radius must have a compiled class (the fit, the labels and the recursive
+// maps do not use it).
+itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out, bool need_class = true) {
   if (!d) return fail(ITC_E_NULL, "descriptor is NULL");
   if (d->height < 1 || d->width < 1)
     return fail(ITC_E_ARG, "height and width must be >= 1 (got %d x %d)", d->height, d->width);
@@ -70,7 +73,7 @@ itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out) {
   if (R < 1) return fail(ITC_E_ARG, "radius must be >= 1 (got %d)", R);
   const bool f64 = d->real_dtype == ITC_F64;
   const int rc = itc::radius_class(R, f64);
-  if (rc < 0)
+  if (rc < 0 && need_class)
     return fail(ITC_E_UNSUPPORTED, "radius %d exceeds the compiled maximum %d for %s", R,
                 f64 ? ITC_MAX_RADIUS_F64 : ITC_MAX_RADIUS_F32, f64 ? "FP64" : "FP32");
   // the kernels address one image and its maps with 32-bit byte offsets
@@ -83,7 +86,7 @@ itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out) {
     return fail(ITC_E_UNSUPPORTED, "image (%llu B) or maps (%llu B) exceed 2 GiB", (unsigned long long)img_bytes,
                 (unsigned long long)map_bytes);
   if (R_out) *R_out = R;
-  if (rc_out) *rc_out = rc;
+  if (rc_out) *rc_out = rc < 0 ? 0 : rc;
   return ITC_OK;
 }
 
@@ -214,7 +217,7 @@ static itc_status fit_common(const itc_lattice_desc* d, const void* maps, const 
                              const void* w_init, int32_t iters, double theta, void* w_out, double* d_trace,
                              double* d_out, int32_t* iters_done, bool write_w, void* stream) {
   int R = 0, rc = 0;
-  itc_status st = check_desc(d, &R, &rc);
+  itc_status st = check_desc(d, &R, &rc, false);
   if (st != ITC_OK) return st;
   if (!maps || !w_init) return fail(ITC_E_NULL, "maps and the codebook must be non-NULL");
   if (write_w && !w_out) return fail(ITC_E_NULL, "w_out must be non-NULL");
@@ -607,7 +610,7 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
 itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,
                              int32_t* labels, void* stream) {
   int R = 0, rc = 0;
-  itc_status st = check_desc(d, &R, &rc);
+  itc_status st = check_desc(d, &R, &rc, false);
   if (st != ITC_OK) return st;
   if (!weights || !w || !labels) return fail(ITC_E_NULL, "weights, w and labels must be non-NULL");
   if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
@@ -628,6 +631,75 @@ itc_status itc_lattice_label_batched(itc_plan* p, const void* weights, const voi
   hipError_t e = itc::launch_label_batched(p->d_images, p->d_ch_rows, (int)p->ch_rows.size(), p->m_max, weights, w,
                                            labels, grid, (hipStream_t)stream);
   if (e != hipSuccess) return device_fail(e, "batched labelling launch");
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// recursive maps (large widths)
+// ---------------------------------------------------------------------------
+static itc_status check_recursive(const itc_lattice_desc* d, int* R, int* rc) {
+  itc_status st = check_desc(d, R, rc, false);
+  if (st != ITC_OK) return st;
+  if (d->real_dtype != ITC_F32) return fail(ITC_E_UNSUPPORTED, "the recursive maps are FP32");
+  if (d->sigma < 0.5) return fail(ITC_E_ARG, "the recursive Gaussian needs sigma >= 0.5 (got %g)", d->sigma);
+  return ITC_OK;
+}
+
+static itc::RecCoeffs rec_coeffs(double sigma) {
+  // Young & van Vliet (1995): q from sigma, then b0..b3
+  const double q = sigma >= 2.5 ? 0.98711 * sigma - 0.96330 : 3.97156 - 4.14554 * std::sqrt(1.0 - 0.26891 * sigma);
+  const double b0 = 1.57825 + 2.44413 * q + 1.4281 * q * q + 0.422205 * q * q * q;
+  const double b1 = 2.44413 * q + 2.85619 * q * q + 1.26661 * q * q * q;
+  const double b2 = -(1.4281 * q * q + 1.26661 * q * q * q);
+  const double b3 = 0.422205 * q * q * q;
+  itc::RecCoeffs c;
+  c.B = 1.0 - (b1 + b2 + b3) / b0;
+  c.a1 = b1 / b0;
+  c.a2 = b2 / b0;
+  c.a3 = b3 / b0;
+  c.gain = std::sqrt(2.0 * M_PI) * sigma;
+  c.m = (int)std::ceil(6.0 * sigma);
+  return c;
+}
+
+static size_t rec_e1_bytes(const itc_lattice_desc& d, int m) {
+  return ((size_t)(d.width + 2 + m) * (size_t)(d.height + 2) * sizeof(double) + 255) / 256 * 256;
+}
+static size_t rec_e2_bytes(const itc_lattice_desc& d, int m) {
+  return ((size_t)(d.height + 2 + m) * (size_t)(d.width + 2) * sizeof(double) + 255) / 256 * 256;
+}
+
+size_t itc_lattice_recursive_maps_bytes(const itc_lattice_desc* d) {
+  int R = 0, rc = 0;
+  if (check_recursive(d, &R, &rc) != ITC_OK) return 0;
+  return maps_bytes_of(*d);
+}
+
+size_t itc_lattice_recursive_work_bytes(const itc_lattice_desc* d) {
+  int R = 0, rc = 0;
+  if (check_recursive(d, &R, &rc) != ITC_OK) return 0;
+  const int m = rec_coeffs(d->sigma).m;
+  return rec_e1_bytes(*d, m) + rec_e2_bytes(*d, m);
+}
+
+itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const void* weights, void* maps,
+                                            double* s_x, void* work, void* stream) {
+  int R = 0, rc = 0;
+  itc_status st = check_recursive(d, &R, &rc);
+  if (st != ITC_OK) return st;
+  if (!weights || !maps || !s_x || !work) return fail(ITC_E_NULL, "weights, maps, s_x and work must be non-NULL");
+  if (!aligned256(maps) || !aligned256(work)) return fail(ITC_E_ARG, "maps and work must be 256-byte aligned");
+  const itc::RecCoeffs c = rec_coeffs(d->sigma);
+  const uint64_t e_elems = (uint64_t)(d->width + 2 + c.m) * (uint64_t)(d->height + 2 + c.m);
+  if (e_elems >= (1ull << 31)) return fail(ITC_E_UNSUPPORTED, "image too large for the recursive maps");
+  ImageDesc im = make_image(*d, R, rc);
+  hipStream_t s = (hipStream_t)stream;
+  double* E1 = (double*)work;
+  double* E2 = (double*)((char*)work + rec_e1_bytes(*d, c.m));
+  hipError_t e = itc::launch_recursive(im, weights, d->weight_scale, d->sigma, c, E1, E2, maps, s);
+  if (e != hipSuccess) return device_fail(e, "recursive maps launch");
+  e = itc::launch_sx_finalize(false, im, maps, s_x, s);
+  if (e != hipSuccess) return device_fail(e, "S_X launch");
   return ok();
 }
 

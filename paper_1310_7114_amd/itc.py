@@ -65,6 +65,9 @@ SIGNATURES = {
     "itc_lattice_divergence_backward_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer": (ctypes.c_int, [_DP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_label": (ctypes.c_int, [_DP, _P, ctypes.c_int32, _P, _P, _P]),
+    "itc_lattice_recursive_maps_bytes": (ctypes.c_size_t, [_DP]),
+    "itc_lattice_recursive_work_bytes": (ctypes.c_size_t, [_DP]),
+    "itc_lattice_precompute_recursive": (ctypes.c_int, [_DP, _P, _P, _P, _P, _P]),
     "itc_lattice_label_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "itc_lattice_literal_work_bytes": (ctypes.c_size_t, [_DP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
     "itc_lattice_literal_fit": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P,
@@ -223,6 +226,28 @@ def chamfer(x: torch.Tensor, a: int = 3, b: int = 4, out: Optional[torch.Tensor]
         out = torch.empty((H, x.stride(0)), dtype=torch.float32, device=x.device)
     _check(load().itc_lattice_chamfer(ctypes.byref(desc), _ptr(x), int(a), int(b), _ptr(out), _stream()))
     return out[:, :W]
+
+
+def precompute_recursive(weights: torch.Tensor, sigma: float, scale: float = 1.0,
+                         work: Optional[torch.Tensor] = None) -> Maps:
+    """Maps A, M_u, M_v and S_X with the recursive Gaussian of width sigma (any sigma >= 0.5)."""
+    if weights.dim() != 2:
+        raise ValueError("weights must be (H, W)")
+    if weights.stride(1) != 1:
+        weights = weights.contiguous()
+    H, W = weights.shape
+    desc = make_desc(H, W, sigma, weights.dtype, torch.float32, scale, 1, pitch=weights.stride(0))
+    nm = load().itc_lattice_recursive_maps_bytes(ctypes.byref(desc))
+    nw = load().itc_lattice_recursive_work_bytes(ctypes.byref(desc))
+    if nm == 0 or nw == 0:
+        raise ItcError(2, load().itc_last_error().decode())
+    if work is None or work.numel() < nw:
+        work = torch.empty(nw, dtype=torch.uint8, device=weights.device)
+    out = Maps(desc, torch.empty(nm, dtype=torch.uint8, device=weights.device),
+               torch.empty(1, dtype=torch.float64, device=weights.device), torch.float32)
+    _check(load().itc_lattice_precompute_recursive(ctypes.byref(desc), _ptr(weights), _ptr(out.buf),
+                                                   _ptr(out.s_x), _ptr(work), _stream()))
+    return out
 
 
 def label(weights: torch.Tensor, w: torch.Tensor, scale: float = 1.0, out: Optional[torch.Tensor] = None,
