@@ -155,6 +155,10 @@ def cpu_legs(cases, seconds):
     t = time.perf_counter()
     O.literal_step(P2, c2.w0, om2, int(np.ceil(3 * om2 - 1e-12)))
     ctx["literal_shapes512_sweep_s"] = time.perf_counter() - t
+    # recursive maps (large widths): the oracle on the 512 x 512 shapes at sigma = 16
+    t = time.perf_counter()
+    O.recursive_maps(c2.weights, 16.0)
+    ctx["recursive_maps_shapes512_s16_s"] = time.perf_counter() - t
 
     # Section 5: the oracle's two-pass chamfer transform on the first silhouettes
     t = time.perf_counter()
@@ -291,6 +295,15 @@ def gpu_extras(dev, cases, itc, synth):
     out["literal_shapes512"] = {"xi": xi2, "omega": om2, "M": c2.M, "sweeps": 20, "ms_total": t20 * 1e3,
                                 "ms_per_sweep": (t20 - t0) / 20 * 1e3, "ms_setup": t0 * 1e3}
     del work
+
+    # maps by recursive filtering: cost per pixel independent of sigma
+    c4 = synth.config4_case(0)
+    x4 = torch.from_numpy(c4.img).to(dev)
+    recs = []
+    for sig in (4.0, 16.0, 40.0):
+        t_r = timed(lambda: itc.precompute_recursive(x4, sig, scale=c4.scale))
+        recs.append({"sigma": sig, "ms": t_r * 1e3, "gpx_per_s": c4.img.size / t_r / 1e9})
+    out["recursive_gray2048"] = recs
 
     c5 = synth.config5_cases(64)
     p = itc.BatchPlan([torch.from_numpy(c.img) for c in c5], [c.M for c in c5], [c.sigma for c in c5],
