@@ -225,6 +225,76 @@ def sample_init(img: np.ndarray, M: int, seed_key, jitter=None) -> np.ndarray:
     return w
 
 
+def ellipsoids_volume(seed_key, D: int, H: int, W: int, n: int = 4, margin: int = 7,
+                      semi=(0.12, 0.3), cover=(0.04, 0.25)) -> np.ndarray:
+    """Binary union of ``n`` axis-rotated filled ellipsoids in a D x H x W volume.
+
+    Centres uniform in the interior, semi-axes U[semi] times the smallest
+    extent, each ellipsoid rotated about the slice axis by U[0, pi); voxels
+    within ``margin`` of a face are cleared. Redrawn until the on-voxel
+    fraction lies in ``cover``.
+    """
+    rng = rng_for(*seed_key)
+    s, u, v = np.meshgrid(np.arange(D, dtype=np.float64), np.arange(H, dtype=np.float64),
+                          np.arange(W, dtype=np.float64), indexing="ij")
+    keep = ((s >= margin) & (s < D - margin) & (u >= margin) & (u < H - margin) & (v >= margin)
+            & (v < W - margin))
+    ext = float(min(D, H, W))
+    for _ in range(1000):
+        m = np.zeros((D, H, W), dtype=bool)
+        for _ in range(n):
+            c = [rng.uniform(margin, n_ - margin) for n_ in (D, H, W)]
+            a, b, cax = rng.uniform(semi[0] * ext, semi[1] * ext, size=3)
+            th = rng.uniform(0.0, math.pi)
+            du, dv = u - c[1], v - c[2]
+            pu = math.cos(th) * du + math.sin(th) * dv
+            pv = -math.sin(th) * du + math.cos(th) * dv
+            m |= ((s - c[0]) / a) ** 2 + (pu / b) ** 2 + (pv / cax) ** 2 <= 1.0
+        m &= keep
+        if cover[0] <= float(m.mean()) <= cover[1]:
+            return m.astype(np.uint8)
+    raise RuntimeError("ellipsoids_volume: no draw met the coverage")
+
+
+def sample_init_volume(vol: np.ndarray, M: int, seed_key) -> np.ndarray:
+    """M distinct voxels with vol > 0, uniform without replacement: (M, 3) float64 of (s, u, v)."""
+    rng = rng_for(*seed_key)
+    on = np.flatnonzero(vol.reshape(-1) > 0)
+    if on.size < M:
+        raise ValueError(f"sample_init_volume: {on.size} on-voxels < M={M}")
+    pick = rng.choice(on, size=M, replace=False)
+    D, H, W = vol.shape
+    return np.stack([pick // (H * W), (pick // W) % H, pick % W], axis=1).astype(np.float64)
+
+
+@dataclass
+class VolumeCase:
+    """One clustering problem on a 3-D lattice: weights = scale * vol."""
+    vol: np.ndarray            # (D, H, W) uint8 stored weights
+    scale: float
+    w0: np.ndarray             # (M, 3) float64 initial codebook (s, u, v)
+    sigma: float
+    R: int
+    iters: int
+    name: str = ""
+
+    @property
+    def weights(self) -> np.ndarray:
+        return self.vol.astype(np.float64) * self.scale
+
+    @property
+    def M(self) -> int:
+        return int(self.w0.shape[0])
+
+
+def volume_case(seed: int = 0, D: int = 48, H: int = 56, W: int = 64, M: int = 24, sigma: float = 2.0,
+                iters: int = 30) -> VolumeCase:
+    """Ellipsoids in a D x H x W volume, M codevectors on on-voxels."""
+    vol = ellipsoids_volume((6, seed), D, H, W)
+    return VolumeCase(vol, 1.0, sample_init_volume(vol, M, (6, seed, 1)), sigma, radius_for(sigma), iters,
+                      name=f"ellipsoids{D}x{H}x{W}-s{seed}")
+
+
 # ----------------------------------------------------------------------------
 # the five workloads
 # ----------------------------------------------------------------------------
