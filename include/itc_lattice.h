@@ -251,6 +251,54 @@ itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const voi
                                             double* s_x, void* work, void* stream);
 
 /* ------------------------------------------------------------------------
+ * 3-D lattices (volumes). The paper develops the method on 2-D lattices and
+ * notes that it carries over to higher-dimensional ones; these entry points
+ * are that carry-over with the readings of the 2-D calls (one width, cubic
+ * window |d_axis| <= R, zero weights outside the lattice, trilinear reads with
+ * off-lattice corners 0, Jacobi sweeps). Coordinates x = (s, u, v): slice,
+ * row, column. Maps and codebooks are FP32; sums of S_X, S_XW, S_W and D FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t depth, height, width; /* lattice extent, each >= 1                          */
+  int32_t radius;               /* R; 0 => ceil(3 sigma); at most ITC_MAX_VOLUME_RADIUS */
+  int64_t row_pitch;            /* elements between rows of the weights (>= width)   */
+  int64_t slice_pitch;          /* elements between slices (>= height * row_pitch)  */
+  itc_dtype weight_dtype;       /* ITC_U8 | ITC_F32 | ITC_F64                        */
+  int32_t reserved;             /* must be 0                                         */
+  double weight_scale;          /* h = weight_scale * stored                         */
+  double sigma;                 /* kernel width (> 0)                                */
+} itc_volume_desc;
+
+#define ITC_MAX_VOLUME_RADIUS 64
+
+/* Bytes of the maps buffer: planes A, M_s, M_u, M_v, each depth x height x
+ * width FP32 contiguous, then library-internal FP64 block sums of S_X;
+ * 0 if d is invalid. */
+size_t itc_volume_maps_bytes(const itc_volume_desc* d);
+/* Bytes of the work buffer of itc_volume_precompute (five FP32 volumes). */
+size_t itc_volume_work_bytes(const itc_volume_desc* d);
+
+/*
+ * Section 3.1 in three dimensions: A = h * G and the moments
+ * M_a(x) = sum_y h(y) (x_a - y_a) G(x - y), a = s, u, v, as chains of 1-D
+ * correlations, and S_X = sum h A (one device double). `maps` and `work`
+ * are device buffers of the sizes above, 256-byte aligned.
+ */
+itc_status itc_volume_precompute(const itc_volume_desc* d, const void* weights, void* maps, double* s_x,
+                                 void* work, void* stream);
+
+/*
+ * Eq. (4) in three dimensions on the volume maps: `iters` Jacobi sweeps of M
+ * codevectors (w_init, w_out: device FP32 [M][3] (s, u, v), may alias), D
+ * before each sweep and after the last in d_trace (device double [iters + 1]
+ * or NULL), early stop when no codevector moves farther than theta (< 0: off),
+ * sweeps done in iters_done (device int32 or NULL). One workgroup.
+ */
+itc_status itc_volume_fit(const itc_volume_desc* d, const void* maps, const double* s_x, int32_t M,
+                          const float* w_init, int32_t iters, double theta, float* w_out, double* d_trace,
+                          int32_t* iters_done, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: n independent images of uneven size, each with its own M,
  * sigma and iteration count, in flat device buffers. A plan is built once per
  * batch layout; its calls launch one persistent kernel each (convolution

@@ -108,6 +108,19 @@ struct SxBlock {
   int32_t img;
   int32_t b;
 };
+// 3-D lattices: one volume (slice, row, column) and its window radius.
+struct VolumeGeom {
+  int32_t D, H, W, R;
+  int64_t row_pitch, slice_pitch;  // elements, of the stored weights
+  double scale, sigma;
+};
+int volume_sx_blocks(int64_t n);
+hipError_t launch_volume_maps(const VolumeGeom& vg, int wdtype, const void* x, float* work, float* maps,
+                              double* sx_blk, double* s_x, hipStream_t s);
+hipError_t launch_volume_fit(const VolumeGeom& vg, const float* maps, const double* s_x, int M, const float* w_init,
+                             int iters, double theta, float* w_out, double* d_trace, int32_t* iters_done,
+                             hipStream_t s);
+
 // Young-van Vliet recursive Gaussian: coefficients, output gain and the
 // zero margin appended to every line.
 struct RecCoeffs {

@@ -703,6 +703,88 @@ itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const voi
   return ok();
 }
 
+// ---------------------------------------------------------------------------
+// 3-D lattices
+// ---------------------------------------------------------------------------
+static itc_status check_volume(const itc_volume_desc* d, itc::VolumeGeom* vg) {
+  if (!d) return fail(ITC_E_NULL, "volume descriptor is NULL");
+  if (d->depth < 1 || d->height < 1 || d->width < 1)
+    return fail(ITC_E_ARG, "depth, height and width must be >= 1 (got %d x %d x %d)", d->depth, d->height, d->width);
+  if (d->row_pitch < d->width) return fail(ITC_E_ARG, "row_pitch %lld < width %d", (long long)d->row_pitch, d->width);
+  if (d->slice_pitch < (int64_t)d->height * d->row_pitch)
+    return fail(ITC_E_ARG, "slice_pitch %lld < height * row_pitch", (long long)d->slice_pitch);
+  if (d->weight_dtype < ITC_U8 || d->weight_dtype > ITC_F64)
+    return fail(ITC_E_ARG, "weight_dtype %d is not ITC_U8/ITC_F32/ITC_F64", d->weight_dtype);
+  if (d->reserved != 0) return fail(ITC_E_ARG, "reserved must be 0");
+  if (!std::isfinite(d->weight_scale)) return fail(ITC_E_ARG, "weight_scale is not finite");
+  if (!(d->sigma > 0.0) || !std::isfinite(d->sigma))
+    return fail(ITC_E_ARG, "sigma must be finite and > 0 (got %g)", d->sigma);
+  if (d->radius < 0) return fail(ITC_E_ARG, "radius must be >= 0 (got %d)", d->radius);
+  const double rr = std::ceil(3.0 * d->sigma - 1e-12);
+  const int R = d->radius > 0 ? d->radius : (rr > ITC_MAX_VOLUME_RADIUS ? ITC_MAX_VOLUME_RADIUS + 1 : (int)rr);
+  if (R < 1) return fail(ITC_E_ARG, "radius must be >= 1");
+  if (R > ITC_MAX_VOLUME_RADIUS) return fail(ITC_E_UNSUPPORTED, "radius %d exceeds %d", R, ITC_MAX_VOLUME_RADIUS);
+  const uint64_t n = (uint64_t)d->depth * d->height * d->width;
+  if (n * 4 * sizeof(float) >= (1ull << 31)) return fail(ITC_E_UNSUPPORTED, "volume maps exceed 2 GiB");
+  if (vg) {
+    vg->D = d->depth;
+    vg->H = d->height;
+    vg->W = d->width;
+    vg->R = R;
+    vg->row_pitch = d->row_pitch;
+    vg->slice_pitch = d->slice_pitch;
+    vg->scale = d->weight_scale;
+    vg->sigma = d->sigma;
+  }
+  return ITC_OK;
+}
+
+static size_t volume_planes_bytes(const itc_volume_desc& d) {
+  return (size_t)4 * d.depth * d.height * d.width * sizeof(float);
+}
+
+size_t itc_volume_maps_bytes(const itc_volume_desc* d) {
+  if (check_volume(d, nullptr) != ITC_OK) return 0;
+  const int64_t n = (int64_t)d->depth * d->height * d->width;
+  return (volume_planes_bytes(*d) + (size_t)itc::volume_sx_blocks(n) * sizeof(double) + 255) / 256 * 256;
+}
+
+size_t itc_volume_work_bytes(const itc_volume_desc* d) {
+  if (check_volume(d, nullptr) != ITC_OK) return 0;
+  return ((size_t)5 * d->depth * d->height * d->width * sizeof(float) + 255) / 256 * 256;
+}
+
+itc_status itc_volume_precompute(const itc_volume_desc* d, const void* weights, void* maps, double* s_x,
+                                 void* work, void* stream) {
+  itc::VolumeGeom vg;
+  itc_status st = check_volume(d, &vg);
+  if (st != ITC_OK) return st;
+  if (!weights || !maps || !s_x || !work) return fail(ITC_E_NULL, "weights, maps, s_x and work must be non-NULL");
+  if (!aligned256(maps) || !aligned256(work)) return fail(ITC_E_ARG, "maps and work must be 256-byte aligned");
+  double* blk = (double*)((char*)maps + volume_planes_bytes(*d));
+  hipError_t e = itc::launch_volume_maps(vg, d->weight_dtype, weights, (float*)work, (float*)maps, blk, s_x,
+                                         (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "volume maps launch");
+  return ok();
+}
+
+itc_status itc_volume_fit(const itc_volume_desc* d, const void* maps, const double* s_x, int32_t M,
+                          const float* w_init, int32_t iters, double theta, float* w_out, double* d_trace,
+                          int32_t* iters_done, void* stream) {
+  itc::VolumeGeom vg;
+  itc_status st = check_volume(d, &vg);
+  if (st != ITC_OK) return st;
+  if (!maps || !s_x || !w_init || !w_out) return fail(ITC_E_NULL, "maps, s_x, w_init and w_out must be non-NULL");
+  if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
+  if (M > ITC_MAX_CODEVECTORS) return fail(ITC_E_UNSUPPORTED, "M %d exceeds %d", M, ITC_MAX_CODEVECTORS);
+  if (iters < 0) return fail(ITC_E_ARG, "iters must be >= 0 (got %d)", iters);
+  if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
+  hipError_t e = itc::launch_volume_fit(vg, (const float*)maps, s_x, M, w_init, iters, theta, w_out, d_trace,
+                                        iters_done, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "volume fit launch");
+  return ok();
+}
+
 static itc_status check_chamfer_mask(int32_t a, int32_t b) {
   if (a < 1 || a > ITC_MAX_CHAMFER_STEP || b < a || b > 2 * a)
     return fail(ITC_E_ARG, "chamfer steps need 1 <= a <= b <= 2a and a <= %d (got a=%d, b=%d)",

@@ -44,6 +44,13 @@ class Batch(ctypes.Structure):
                 ("iters", ctypes.POINTER(ctypes.c_int32))]
 
 
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("radius", ctypes.c_int32), ("row_pitch", ctypes.c_int64), ("slice_pitch", ctypes.c_int64),
+                ("weight_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32), ("weight_scale", ctypes.c_double),
+                ("sigma", ctypes.c_double)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(Desc)
@@ -66,6 +73,11 @@ SIGNATURES = {
     "itc_lattice_chamfer": (ctypes.c_int, [_DP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_label": (ctypes.c_int, [_DP, _P, ctypes.c_int32, _P, _P, _P]),
     "itc_lattice_recursive_maps_bytes": (ctypes.c_size_t, [_DP]),
+    "itc_volume_maps_bytes": (ctypes.c_size_t, [ctypes.POINTER(VolumeDesc)]),
+    "itc_volume_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(VolumeDesc)]),
+    "itc_volume_precompute": (ctypes.c_int, [ctypes.POINTER(VolumeDesc), _P, _P, _P, _P, _P]),
+    "itc_volume_fit": (ctypes.c_int, [ctypes.POINTER(VolumeDesc), _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
+                                      ctypes.c_double, _P, _P, _P, _P]),
     "itc_lattice_recursive_work_bytes": (ctypes.c_size_t, [_DP]),
     "itc_lattice_precompute_recursive": (ctypes.c_int, [_DP, _P, _P, _P, _P, _P]),
     "itc_lattice_label_batched": (ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -248,6 +260,54 @@ def precompute_recursive(weights: torch.Tensor, sigma: float, scale: float = 1.0
     _check(load().itc_lattice_precompute_recursive(ctypes.byref(desc), _ptr(weights), _ptr(out.buf),
                                                    _ptr(out.s_x), _ptr(work), _stream()))
     return out
+
+
+class VolumeMaps:
+    """Device maps A, M_s, M_u, M_v of a volume (FP32, each D x H x W) and S_X."""
+
+    def __init__(self, desc, buf, s_x):
+        self.desc, self.buf, self.s_x = desc, buf, s_x
+
+    def planes(self):
+        n = self.desc.depth * self.desc.height * self.desc.width
+        f = self.buf[: 16 * n].view(torch.float32)
+        shape = (self.desc.depth, self.desc.height, self.desc.width)
+        return [f[i * n:(i + 1) * n].view(shape) for i in range(4)]
+
+
+def volume_precompute(vol: torch.Tensor, sigma: float, scale: float = 1.0, radius: int = 0,
+                      work: Optional[torch.Tensor] = None) -> VolumeMaps:
+    """Maps of a (D, H, W) weight volume (3-D lattice)."""
+    if vol.dim() != 3:
+        raise ValueError("vol must be (D, H, W)")
+    if vol.stride(2) != 1:
+        vol = vol.contiguous()
+    D, H, W = vol.shape
+    desc = VolumeDesc(int(D), int(H), int(W), int(radius), int(vol.stride(1)), int(vol.stride(0)),
+                      _WDT[vol.dtype], 0, float(scale), float(sigma))
+    nm = load().itc_volume_maps_bytes(ctypes.byref(desc))
+    nw = load().itc_volume_work_bytes(ctypes.byref(desc))
+    if nm == 0 or nw == 0:
+        raise ItcError(2, load().itc_last_error().decode())
+    if work is None or work.numel() < nw:
+        work = torch.empty(nw, dtype=torch.uint8, device=vol.device)
+    out = VolumeMaps(desc, torch.empty(nm, dtype=torch.uint8, device=vol.device),
+                     torch.empty(1, dtype=torch.float64, device=vol.device))
+    _check(load().itc_volume_precompute(ctypes.byref(desc), _ptr(vol), _ptr(out.buf), _ptr(out.s_x), _ptr(work),
+                                        _stream()))
+    return out
+
+
+def volume_fit(maps: VolumeMaps, w_init: torch.Tensor, iters: int, theta: float = -1.0, trace: bool = True):
+    """Sweeps of eq. (4) on a volume: (W (M, 3) float32, D trace or None, sweeps done tensor)."""
+    w_init = w_init.to(torch.float32).contiguous()
+    M = int(w_init.shape[0])
+    w_out = torch.empty_like(w_init)
+    d_trace = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=w_init.device) if trace else None
+    done = torch.zeros(1, dtype=torch.int32, device=w_init.device)
+    _check(load().itc_volume_fit(ctypes.byref(maps.desc), _ptr(maps.buf), _ptr(maps.s_x), M, _ptr(w_init),
+                                 int(iters), float(theta), _ptr(w_out), _ptr(d_trace), _ptr(done), _stream()))
+    return w_out, d_trace, done
 
 
 def label(weights: torch.Tensor, w: torch.Tensor, scale: float = 1.0, out: Optional[torch.Tensor] = None,

@@ -163,6 +163,30 @@ def test_label_arguments(itc):
     assert lib.itc_lattice_label_batched(None, P, P, P, None) == 1
 
 
+def test_volume_arguments(itc):
+    lib = itc.load()
+    assert ctypes.sizeof(itc.VolumeDesc) == 56
+    P = ctypes.c_void_p(256)
+    d = itc.VolumeDesc(8, 9, 10, 0, 10, 90, 0, 0, 1.0, 2.0)
+    n = lib.itc_volume_maps_bytes(ctypes.byref(d))
+    assert n == (4 * 720 * 4 + 8 * 1 + 255) // 256 * 256
+    assert lib.itc_volume_work_bytes(ctypes.byref(d)) == (5 * 720 * 4 + 255) // 256 * 256
+    bad = [("depth", 0, 2), ("row_pitch", 9, 2), ("slice_pitch", 80, 2), ("weight_dtype", 9, 2), ("reserved", 1, 2),
+           ("sigma", 0.0, 2), ("radius", -1, 2), ("radius", 65, 3), ("sigma", 30.0, 3)]
+    for field, value, status in bad:
+        e = itc.VolumeDesc(8, 9, 10, 0, 10, 90, 0, 0, 1.0, 2.0)
+        setattr(e, field, value)
+        assert lib.itc_volume_maps_bytes(ctypes.byref(e)) == 0, field
+        assert lib.itc_volume_precompute(ctypes.byref(e), P, P, P, P, None) == status, field
+    assert lib.itc_volume_precompute(ctypes.byref(d), None, P, P, P, None) == 1
+    assert lib.itc_volume_precompute(ctypes.byref(d), P, ctypes.c_void_p(260), P, P, None) == 2
+    fit = lib.itc_volume_fit
+    assert fit(ctypes.byref(d), P, P, 0, P, 5, -1.0, P, None, None, None) == 2
+    assert fit(ctypes.byref(d), P, P, 1025, P, 5, -1.0, P, None, None, None) == 3
+    assert fit(ctypes.byref(d), P, None, 4, P, 5, -1.0, P, None, None, None) == 1
+    assert fit(ctypes.byref(d), P, P, 4, P, -2, -1.0, P, None, None, None) == 2
+
+
 def test_plan_rejects_bad_batches(itc):
     lib = itc.load()
     h = ctypes.c_void_p()
