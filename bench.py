@@ -160,6 +160,13 @@ def cpu_legs(cases, seconds):
     O.recursive_maps(c2.weights, 16.0)
     ctx["recursive_maps_shapes512_s16_s"] = time.perf_counter() - t
 
+    # 3-D lattice: the oracle's maps and fit on a 48 x 56 x 64 volume (M = 24, 30 sweeps)
+    from paper_1310_7114_amd import synth as _s
+    vc = _s.volume_case(0)
+    t = time.perf_counter()
+    O.fit_volume(vc.weights, vc.w0, vc.sigma, vc.R, vc.iters)
+    ctx["volume_48x56x64_fit_s"] = time.perf_counter() - t
+
     # Section 5: the oracle's two-pass chamfer transform on the first silhouettes
     t = time.perf_counter()
     k3, px3 = 0, 0
@@ -304,6 +311,18 @@ def gpu_extras(dev, cases, itc, synth):
         t_r = timed(lambda: itc.precompute_recursive(x4, sig, scale=c4.scale))
         recs.append({"sigma": sig, "ms": t_r * 1e3, "gpx_per_s": c4.img.size / t_r / 1e9})
     out["recursive_gray2048"] = recs
+
+    # 3-D lattice: a 96 x 192 x 256 ellipsoid volume, sigma = 2, M = 64, 50 sweeps
+    vc = synth.volume_case(0, D=96, H=192, W=256, M=64, iters=50)
+    xv = torch.from_numpy(vc.vol).to(dev)
+    wv0 = torch.from_numpy(vc.w0).to(dev)
+    vm = itc.volume_precompute(xv, vc.sigma)
+    t_vm = timed(lambda: itc.volume_precompute(xv, vc.sigma))
+    t_vf = timed(lambda: itc.volume_fit(vm, wv0, vc.iters), reps=3)
+    out["volume_96x192x256"] = {"voxels": int(vc.vol.size), "M": vc.M, "sweeps": vc.iters, "maps_ms": t_vm * 1e3,
+                                "maps_gvox_per_s": vc.vol.size / t_vm / 1e9, "fit_ms": t_vf * 1e3,
+                                "volumes_per_s": 1.0 / (t_vm + t_vf)}
+    del vm
 
     c5 = synth.config5_cases(64)
     p = itc.BatchPlan([torch.from_numpy(c.img) for c in c5], [c.M for c in c5], [c.sigma for c in c5],
