@@ -269,13 +269,13 @@ typedef struct {
   double sigma;                 /* kernel width (> 0)                                */
 } itc_volume_desc;
 
-#define ITC_MAX_VOLUME_RADIUS 64
+#define ITC_MAX_VOLUME_RADIUS 32
 
 /* Bytes of the maps buffer: planes A, M_s, M_u, M_v, each depth x height x
  * width FP32 contiguous, then library-internal FP64 block sums of S_X;
  * 0 if d is invalid. */
 size_t itc_volume_maps_bytes(const itc_volume_desc* d);
-/* Bytes of the work buffer of itc_volume_precompute (five FP32 volumes). */
+/* Bytes of the work buffer of itc_volume_precompute (three FP32 volumes). */
 size_t itc_volume_work_bytes(const itc_volume_desc* d);
 
 /*

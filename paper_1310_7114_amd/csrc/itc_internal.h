@@ -114,7 +114,7 @@ struct VolumeGeom {
   int64_t row_pitch, slice_pitch;  // elements, of the stored weights
   double scale, sigma;
 };
-int volume_sx_blocks(int64_t n);
+int volume_sx_blocks(const VolumeGeom& vg);  // FP64 partials of S_X after the planes
 hipError_t launch_volume_maps(const VolumeGeom& vg, int wdtype, const void* x, float* work, float* maps,
                               double* sx_blk, double* s_x, hipStream_t s);
 hipError_t launch_volume_fit(const VolumeGeom& vg, const float* maps, const double* s_x, int M, const float* w_init,

@@ -724,6 +724,7 @@ static itc_status check_volume(const itc_volume_desc* d, itc::VolumeGeom* vg) {
   const int R = d->radius > 0 ? d->radius : (rr > ITC_MAX_VOLUME_RADIUS ? ITC_MAX_VOLUME_RADIUS + 1 : (int)rr);
   if (R < 1) return fail(ITC_E_ARG, "radius must be >= 1");
   if (R > ITC_MAX_VOLUME_RADIUS) return fail(ITC_E_UNSUPPORTED, "radius %d exceeds %d", R, ITC_MAX_VOLUME_RADIUS);
+  static_assert(ITC_MAX_VOLUME_RADIUS == 32, "the volume kernels hold taps for radii up to 32");
   const uint64_t n = (uint64_t)d->depth * d->height * d->width;
   if (n * 4 * sizeof(float) >= (1ull << 31)) return fail(ITC_E_UNSUPPORTED, "volume maps exceed 2 GiB");
   if (vg) {
@@ -744,14 +745,14 @@ static size_t volume_planes_bytes(const itc_volume_desc& d) {
 }
 
 size_t itc_volume_maps_bytes(const itc_volume_desc* d) {
-  if (check_volume(d, nullptr) != ITC_OK) return 0;
-  const int64_t n = (int64_t)d->depth * d->height * d->width;
-  return (volume_planes_bytes(*d) + (size_t)itc::volume_sx_blocks(n) * sizeof(double) + 255) / 256 * 256;
+  itc::VolumeGeom vg;
+  if (check_volume(d, &vg) != ITC_OK) return 0;
+  return (volume_planes_bytes(*d) + (size_t)itc::volume_sx_blocks(vg) * sizeof(double) + 255) / 256 * 256;
 }
 
 size_t itc_volume_work_bytes(const itc_volume_desc* d) {
   if (check_volume(d, nullptr) != ITC_OK) return 0;
-  return ((size_t)5 * d->depth * d->height * d->width * sizeof(float) + 255) / 256 * 256;
+  return ((size_t)3 * d->depth * d->height * d->width * sizeof(float) + 255) / 256 * 256;
 }
 
 itc_status itc_volume_precompute(const itc_volume_desc* d, const void* weights, void* maps, double* s_x,

@@ -169,10 +169,11 @@ def test_volume_arguments(itc):
     P = ctypes.c_void_p(256)
     d = itc.VolumeDesc(8, 9, 10, 0, 10, 90, 0, 0, 1.0, 2.0)
     n = lib.itc_volume_maps_bytes(ctypes.byref(d))
-    assert n == (4 * 720 * 4 + 8 * 1 + 255) // 256 * 256
-    assert lib.itc_volume_work_bytes(ctypes.byref(d)) == (5 * 720 * 4 + 255) // 256 * 256
+    # FP64 S_X partials: one per workgroup of the depth pass (64 columns x 4 rows x 8 slices)
+    assert n == (4 * 720 * 4 + 8 * (1 * 3 * 1) + 255) // 256 * 256
+    assert lib.itc_volume_work_bytes(ctypes.byref(d)) == (3 * 720 * 4 + 255) // 256 * 256
     bad = [("depth", 0, 2), ("row_pitch", 9, 2), ("slice_pitch", 80, 2), ("weight_dtype", 9, 2), ("reserved", 1, 2),
-           ("sigma", 0.0, 2), ("radius", -1, 2), ("radius", 65, 3), ("sigma", 30.0, 3)]
+           ("sigma", 0.0, 2), ("radius", -1, 2), ("radius", 33, 3), ("sigma", 30.0, 3)]
     for field, value, status in bad:
         e = itc.VolumeDesc(8, 9, 10, 0, 10, 90, 0, 0, 1.0, 2.0)
         setattr(e, field, value)

@@ -38,6 +38,11 @@ CASES = [
      0.5, 0, None),
     ("depth1_64x64", lambda: S.config1_case(1).img[None].copy(), 2.0, 1.0, 0, None),
     ("tiny1x1x1", lambda: np.ones((1, 1, 1), np.uint8), 1.0, 1.0, 0, None),
+    # the wider in-plane staging classes (radius 9..16 and 17..32), ragged tiles
+    ("ellipsoids_s4_r12", lambda: S.volume_case(4, D=30, H=40, W=72).vol, 4.0, 1.0, 0, (1, 3)),
+    ("f64_s8_r32", lambda: np.random.default_rng(5).uniform(size=(19, 70, 90)), 8.0, 2.0, 32, None),
+    # radius 2: the column passes take the zero-padded window instead of the ramps
+    ("u8_s06_r2", lambda: S.volume_case(1, D=30, H=36, W=40).vol, 0.6, 1.0, 0, None),
 ]
 
 
@@ -89,4 +94,4 @@ def test_volume_fit_many_codevectors_and_theta(gpu_lib):
 def test_volume_rejects(gpu_lib):
     x = torch.ones((4, 4, 4), dtype=torch.uint8, device="cuda")
     with pytest.raises(gpu_lib.ItcError):
-        gpu_lib.volume_precompute(x, 30.0)  # radius 90 > 64
+        gpu_lib.volume_precompute(x, 30.0)  # radius 90 > 32
