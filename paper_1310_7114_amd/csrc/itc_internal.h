@@ -123,12 +123,17 @@ hipError_t launch_volume_fit(const VolumeGeom& vg, const float* maps, const doub
 
 // Young-van Vliet recursive Gaussian: coefficients, output gain and the
 // zero margin appended to every line.
+// Recursive Gaussian: w[n] = B x[n] + a1 w[n-1] + a2 w[n-2] + a3 w[n-3] per
+// direction, output times gain; lines padded by m zeros; P = A^REC_SEG
+// (row-major) for the companion matrix A of (a1, a2, a3).
+constexpr int REC_SEG = 64;
 struct RecCoeffs {
   double B, a1, a2, a3, gain;
+  double P[9];
   int m;
 };
 hipError_t launch_recursive(const ImageDesc& im, const void* x, double scale, double sigma, const RecCoeffs& rc,
-                            double* E1, double* E2, void* maps, hipStream_t s);
+                            double* E1, double* E2, double* Z, void* maps, hipStream_t s);
 
 // Algorithm 1 (eq. (6) on the lattice): device pointers into the caller's
 // work buffer and the sweep parameters.

@@ -659,6 +659,15 @@ static itc::RecCoeffs rec_coeffs(double sigma) {
   c.a3 = b3 / b0;
   c.gain = std::sqrt(2.0 * M_PI) * sigma;
   c.m = (int)std::ceil(6.0 * sigma);
+  // P = A^REC_SEG by repeated squaring (REC_SEG is a power of two)
+  double P[9] = {c.a1, c.a2, c.a3, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+  for (int n = 1; n < itc::REC_SEG; n *= 2) {
+    double Q[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q[3 * i + j] = P[3 * i] * P[j] + P[3 * i + 1] * P[3 + j] + P[3 * i + 2] * P[6 + j];
+    std::copy(Q, Q + 9, P);
+  }
+  std::copy(P, P + 9, c.P);
   return c;
 }
 
@@ -667,6 +676,12 @@ static size_t rec_e1_bytes(const itc_lattice_desc& d, int m) {
 }
 static size_t rec_e2_bytes(const itc_lattice_desc& d, int m) {
   return ((size_t)(d.height + 2 + m) * (size_t)(d.width + 2) * sizeof(double) + 255) / 256 * 256;
+}
+// segment states of either pass: [segments][3][columns] doubles
+static size_t rec_z_bytes(const itc_lattice_desc& d, int m) {
+  const size_t z1 = (size_t)((d.width + 2 + m + itc::REC_SEG - 1) / itc::REC_SEG) * (size_t)(d.height + 2);
+  const size_t z2 = (size_t)((d.height + 2 + m + itc::REC_SEG - 1) / itc::REC_SEG) * (size_t)(d.width + 2);
+  return (std::max(z1, z2) * 3 * sizeof(double) + 255) / 256 * 256;
 }
 
 size_t itc_lattice_recursive_maps_bytes(const itc_lattice_desc* d) {
@@ -679,7 +694,7 @@ size_t itc_lattice_recursive_work_bytes(const itc_lattice_desc* d) {
   int R = 0, rc = 0;
   if (check_recursive(d, &R, &rc) != ITC_OK) return 0;
   const int m = rec_coeffs(d->sigma).m;
-  return rec_e1_bytes(*d, m) + rec_e2_bytes(*d, m);
+  return rec_e1_bytes(*d, m) + rec_e2_bytes(*d, m) + rec_z_bytes(*d, m);
 }
 
 itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const void* weights, void* maps,
@@ -696,7 +711,8 @@ itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const voi
   hipStream_t s = (hipStream_t)stream;
   double* E1 = (double*)work;
   double* E2 = (double*)((char*)work + rec_e1_bytes(*d, c.m));
-  hipError_t e = itc::launch_recursive(im, weights, d->weight_scale, d->sigma, c, E1, E2, maps, s);
+  double* Z = (double*)((char*)E2 + rec_e2_bytes(*d, c.m));
+  hipError_t e = itc::launch_recursive(im, weights, d->weight_scale, d->sigma, c, E1, E2, Z, maps, s);
   if (e != hipSuccess) return device_fail(e, "recursive maps launch");
   e = itc::launch_sx_finalize(false, im, maps, s_x, s);
   if (e != hipSuccess) return device_fail(e, "S_X launch");

@@ -13,10 +13,10 @@
 // ring; M = -sigma^2 grad A by central differences (exact for a Gaussian
 // kernel: sum_y h(y) (x - y) g(x - y) = -sigma^2 d/dx sum_y h(y) g(x - y)).
 //
-// Both passes run down columns (one lane per column, coalesced rows), so the
+// Both passes run down columns (lanes along columns, coalesced rows), so the
 // image is first transposed into an FP64 buffer E1 (rows = v), filtered,
 // transposed into E2 (rows = u), filtered, and the maps and S_X partials are
-// read off E2. The recursions run in FP64.
+// read off E2. The recursions run in FP64, segment-parallel along the lines.
 #include "itc_device.h"
 
 namespace itc {
@@ -65,48 +65,125 @@ __global__ void __launch_bounds__(RT * 8) rec_transpose_kernel(const double* __r
   }
 }
 
-// Causal then anticausal pass down every column of E (rows x cols), in place.
+// The recursions run down columns of E (rows x cols, one lane per column),
+// split into segments of REC_SEG rows so that every segment of every column
+// has a lane. With the state z = (w[n-1], w[n-2], w[n-3]) the recursion is
+// linear, z' = A z + B x e1 with the companion matrix A of (a1, a2, a3), so
+// the state after a segment is A^REC_SEG z_start plus the state the segment
+// reaches from zero. Per direction: every segment's zero-state end, a scan
+// over the segments of each column for the true start states, and a rerun of
+// every segment from its start state that writes the values.
 constexpr int RB = 8;
 
-__global__ void __launch_bounds__(64) rec_filter_kernel(double* __restrict__ E, int64_t p, int rows, int cols,
-                                                        double B, double a1, double a2, double a3, double gain) {
+// Recursion over rows [lo, hi) of one column, ascending (dir > 0) or
+// descending, from and into (z1, z2, z3); with OUT the values times `gain`
+// replace the inputs.
+template <bool OUT>
+__device__ __forceinline__ void rec_run(double* col, int64_t p, int lo, int hi, int dir, const RecCoeffs& rc,
+                                        double gain, double& z1, double& z2, double& z3) {
+  const int n = hi - lo;
+  for (int k0 = 0; k0 < n; k0 += RB) {
+    double v[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int r = dir > 0 ? lo + k0 + k : hi - 1 - k0 - k;
+      v[k] = k0 + k < n ? col[(int64_t)r * p] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      if (k0 + k < n) {  // uniform: every lane runs the same segment
+        const double w = fma(rc.a1, z1, fma(rc.a2, z2, fma(rc.a3, z3, rc.B * v[k])));
+        z3 = z2;
+        z2 = z1;
+        z1 = w;
+        v[k] = w * gain;
+      }
+    }
+    if (OUT) {
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        const int r = dir > 0 ? lo + k0 + k : hi - 1 - k0 - k;
+        if (k0 + k < n) col[(int64_t)r * p] = v[k];
+      }
+    }
+  }
+}
+
+// Z layout: [segment][3][cols].
+__device__ __forceinline__ double* zat(double* Z, int sg, int q, int cols, int c) {
+  return Z + ((int64_t)sg * 3 + q) * cols + c;
+}
+
+// Zero-state end of every segment along dir (blockIdx.y = segment).
+__global__ void __launch_bounds__(64) rec_seg_end_kernel(double* __restrict__ E, int64_t p, int rows, int cols,
+                                                         RecCoeffs rc, int dir, double* __restrict__ Z) {
+  const int c = blockIdx.x * 64 + threadIdx.x, sg = blockIdx.y;
+  if (c >= cols) return;
+  const int lo = sg * REC_SEG, hi = min(lo + REC_SEG, rows);
+  double z1 = 0.0, z2 = 0.0, z3 = 0.0;
+  rec_run<false>(E + c, p, lo, hi, dir, rc, 1.0, z1, z2, z3);
+  *zat(Z, sg, 0, cols, c) = z1;
+  *zat(Z, sg, 1, cols, c) = z2;
+  *zat(Z, sg, 2, cols, c) = z3;
+}
+
+// Start states from the zero-state ends, in place: segments in the order of
+// dir, z_start(first) = 0, z_start(next) = A^REC_SEG z_start + z_end0. Only
+// the segment last in that order can be shorter, and its end is not carried.
+__global__ void __launch_bounds__(64) rec_seg_scan_kernel(double* __restrict__ Z, int nseg, int cols, RecCoeffs rc,
+                                                          int dir) {
   const int c = blockIdx.x * 64 + threadIdx.x;
   if (c >= cols) return;
-  double* col = E + c;
-  double w1 = 0.0, w2 = 0.0, w3 = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += RB) {
-    double v[RB];
-#pragma unroll
-    for (int k = 0; k < RB; ++k) v[k] = r0 + k < rows ? col[(int64_t)(r0 + k) * p] : 0.0;
-#pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      const double w = B * v[k] + a1 * w1 + a2 * w2 + a3 * w3;
-      w3 = w2;
-      w2 = w1;
-      w1 = w;
-      v[k] = w;
-    }
-#pragma unroll
-    for (int k = 0; k < RB; ++k)
-      if (r0 + k < rows) col[(int64_t)(r0 + k) * p] = v[k];
+  const double* P = rc.P;
+  double z1 = 0.0, z2 = 0.0, z3 = 0.0;
+  for (int i = 0; i < nseg; ++i) {
+    const int sg = dir > 0 ? i : nseg - 1 - i;
+    double* e1 = zat(Z, sg, 0, cols, c);
+    double* e2 = zat(Z, sg, 1, cols, c);
+    double* e3 = zat(Z, sg, 2, cols, c);
+    const double f1 = *e1, f2 = *e2, f3 = *e3;
+    *e1 = z1;
+    *e2 = z2;
+    *e3 = z3;
+    const double n1 = fma(P[0], z1, fma(P[1], z2, fma(P[2], z3, f1)));
+    const double n2 = fma(P[3], z1, fma(P[4], z2, fma(P[5], z3, f2)));
+    const double n3 = fma(P[6], z1, fma(P[7], z2, fma(P[8], z3, f3)));
+    z1 = n1;
+    z2 = n2;
+    z3 = n3;
   }
-  double y1 = 0.0, y2 = 0.0, y3 = 0.0;
-  for (int r1 = rows - 1; r1 >= 0; r1 -= RB) {
-    double v[RB];
-#pragma unroll
-    for (int k = 0; k < RB; ++k) v[k] = r1 - k >= 0 ? col[(int64_t)(r1 - k) * p] : 0.0;
-#pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      const double y = B * v[k] + a1 * y1 + a2 * y2 + a3 * y3;
-      y3 = y2;
-      y2 = y1;
-      y1 = y;
-      v[k] = y * gain;
-    }
-#pragma unroll
-    for (int k = 0; k < RB; ++k)
-      if (r1 - k >= 0) col[(int64_t)(r1 - k) * p] = v[k];
+}
+
+// Rerun of every segment from its start state. Causal (dir > 0): writes w,
+// then leaves in Z the zero-state end of the anticausal pass over the same
+// rows (this lane's own values, just written). Anticausal: writes y * gain.
+__global__ void __launch_bounds__(64) rec_seg_apply_kernel(double* __restrict__ E, int64_t p, int rows, int cols,
+                                                           RecCoeffs rc, int dir, double* __restrict__ Z) {
+  const int c = blockIdx.x * 64 + threadIdx.x, sg = blockIdx.y;
+  if (c >= cols) return;
+  const int lo = sg * REC_SEG, hi = min(lo + REC_SEG, rows);
+  double z1 = *zat(Z, sg, 0, cols, c), z2 = *zat(Z, sg, 1, cols, c), z3 = *zat(Z, sg, 2, cols, c);
+  if (dir > 0) {
+    rec_run<true>(E + c, p, lo, hi, 1, rc, 1.0, z1, z2, z3);
+    z1 = z2 = z3 = 0.0;
+    rec_run<false>(E + c, p, lo, hi, -1, rc, 1.0, z1, z2, z3);
+    *zat(Z, sg, 0, cols, c) = z1;
+    *zat(Z, sg, 1, cols, c) = z2;
+    *zat(Z, sg, 2, cols, c) = z3;
+  } else {
+    rec_run<true>(E + c, p, lo, hi, -1, rc, rc.gain, z1, z2, z3);
   }
+}
+
+// Causal then anticausal pass down every column of E, in place.
+void rec_filter(double* E, int64_t p, int rows, int cols, const RecCoeffs& rc, double* Z, hipStream_t s) {
+  const dim3 g((cols + 63) / 64, (rows + REC_SEG - 1) / REC_SEG), b(64);
+  const int nseg = (int)g.y;
+  hipLaunchKernelGGL(rec_seg_end_kernel, g, b, 0, s, E, p, rows, cols, rc, 1, Z);
+  hipLaunchKernelGGL(rec_seg_scan_kernel, dim3(g.x), b, 0, s, Z, nseg, cols, rc, 1);
+  hipLaunchKernelGGL(rec_seg_apply_kernel, g, b, 0, s, E, p, rows, cols, rc, 1, Z);
+  hipLaunchKernelGGL(rec_seg_scan_kernel, dim3(g.x), b, 0, s, Z, nseg, cols, rc, -1);
+  hipLaunchKernelGGL(rec_seg_apply_kernel, g, b, 0, s, E, p, rows, cols, rc, -1, Z);
 }
 
 // Maps (FP32 planes, map pitch) and S_X partials from the filtered E2:
@@ -146,19 +223,17 @@ __global__ void __launch_bounds__(64) rec_maps_kernel(const double* __restrict__
 
 template <typename WT>
 hipError_t launch_recursive_t(const ImageDesc& im, const void* x, double scale, double sigma, const RecCoeffs& rc,
-                              double* E1, double* E2, void* maps, hipStream_t s) {
+                              double* E1, double* E2, double* Z, void* maps, hipStream_t s) {
   const int H = im.H, W = im.W;
   const int rows1 = W + 2 + rc.m, cols1 = H + 2;
   const int rows2 = H + 2 + rc.m, cols2 = W + 2;
   const int64_t p1 = cols1, p2 = cols2;
   hipLaunchKernelGGL(rec_load_kernel<WT>, dim3((cols1 + RT - 1) / RT, (rows1 + RT - 1) / RT), dim3(RT * 8), 0, s,
                      (const WT*)x, im.pitch, scale, H, W, E1, p1, rows1);
-  hipLaunchKernelGGL(rec_filter_kernel, dim3((cols1 + 63) / 64), dim3(64), 0, s, E1, p1, rows1, cols1, rc.B, rc.a1,
-                     rc.a2, rc.a3, rc.gain);
+  rec_filter(E1, p1, rows1, cols1, rc, Z, s);
   hipLaunchKernelGGL(rec_transpose_kernel, dim3((cols2 + RT - 1) / RT, (rows2 + RT - 1) / RT), dim3(RT * 8), 0, s,
                      (const double*)E1, p1, H, W, E2, p2, rows2);
-  hipLaunchKernelGGL(rec_filter_kernel, dim3((cols2 + 63) / 64), dim3(64), 0, s, E2, p2, rows2, cols2, rc.B, rc.a1,
-                     rc.a2, rc.a3, rc.gain);
+  rec_filter(E2, p2, rows2, cols2, rc, Z, s);
   hipLaunchKernelGGL(rec_maps_kernel<WT>, dim3((unsigned)(im.map_pitch / 64), (unsigned)im.ngroups), dim3(64), 0,
                      s, (const double*)E2, p2, (const WT*)x, im.pitch, scale, sigma, im, (char*)maps);
   return hipGetLastError();
@@ -167,11 +242,11 @@ hipError_t launch_recursive_t(const ImageDesc& im, const void* x, double scale, 
 }  // namespace
 
 hipError_t launch_recursive(const ImageDesc& im, const void* x, double scale, double sigma, const RecCoeffs& rc,
-                            double* E1, double* E2, void* maps, hipStream_t s) {
+                            double* E1, double* E2, double* Z, void* maps, hipStream_t s) {
   switch (im.wdtype) {
-    case 0: return launch_recursive_t<uint8_t>(im, x, scale, sigma, rc, E1, E2, maps, s);
-    case 1: return launch_recursive_t<float>(im, x, scale, sigma, rc, E1, E2, maps, s);
-    default: return launch_recursive_t<double>(im, x, scale, sigma, rc, E1, E2, maps, s);
+    case 0: return launch_recursive_t<uint8_t>(im, x, scale, sigma, rc, E1, E2, Z, maps, s);
+    case 1: return launch_recursive_t<float>(im, x, scale, sigma, rc, E1, E2, Z, maps, s);
+    default: return launch_recursive_t<double>(im, x, scale, sigma, rc, E1, E2, Z, maps, s);
   }
 }
 
