@@ -91,6 +91,20 @@ def test_volume_fit_many_codevectors_and_theta(gpu_lib):
     assert float(np.linalg.norm(w.cpu().double().numpy() - Wt, axis=1).max()) <= 1e-3
 
 
+@pytest.mark.parametrize("M", [1, 3, 12, 64, 100, 200, 300])
+def test_volume_fit_lane_layouts(gpu_lib, M):
+    """Every layout of the fit: 64, 32, 16, 4, 2 and 1 lanes per codevector,
+    and two codevectors per thread (M = 300), against the oracle for 3 sweeps."""
+    case = S.volume_case(5, D=32, H=40, W=48, M=M, iters=3)
+    m, _, _ = gpu_maps(gpu_lib, case.vol, case.sigma)
+    W_ref, tr_ref, _, _ = O.fit_volume(case.weights, case.w0, case.sigma, case.R, case.iters)
+    w, tr, done = gpu_lib.volume_fit(m, torch.from_numpy(case.w0).cuda(), case.iters)
+    torch.cuda.synchronize()
+    assert int(done.cpu()[0]) == case.iters
+    assert float(np.linalg.norm(w.cpu().double().numpy() - W_ref, axis=1).max()) <= 1e-3
+    assert np.abs(tr.cpu().numpy() - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
+
+
 def test_volume_rejects(gpu_lib):
     x = torch.ones((4, 4, 4), dtype=torch.uint8, device="cuda")
     with pytest.raises(gpu_lib.ItcError):
