@@ -348,6 +348,8 @@ def parse():
                    help="skip the secondary measurements (copy peak, per-sigma conv, single-image workloads)")
     p.add_argument("--eager", action="store_true",
                    help="launch on the stream instead of replaying a HIP graph (for counter profiling)")
+    p.add_argument("--no-tune", action="store_true",
+                   help="keep the default convolution tile shapes instead of autotuning them")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     return p.parse_args()
@@ -391,6 +393,13 @@ def main():
     plan = itc.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
                          [c.sigma for c in cases], [c.iters for c in cases], device=dev)
     w0 = plan.pack_codebooks([c.w0 for c in cases], device=dev)
+    # tile shapes of the convolution per radius class, chosen on this batch
+    # before anything is captured or timed (not part of the timed step)
+    tuned = None
+    if not args.no_tune:
+        from paper_1310_7114_amd import autotune
+        tuned = {str(k): v for k, v in autotune.tune_conv(plan).items()}
+        print(f"[bench] autotuned convolution shapes {tuned}", file=sys.stderr, flush=True)
     w = torch.empty_like(w0)
     sx = torch.empty(n, dtype=torch.float64, device=dev)
     dd = torch.empty(n, dtype=torch.float64, device=dev)
@@ -539,6 +548,7 @@ def main():
         "phases_ms": {"conv": conv_s * 1e3, "fit_and_divergence": fit_s * 1e3},
         "per_image": per_image,
         "pcie_inclusive": pcie,
+        "autotune": tuned,
         "batched_over_per_image": (value / per_image["value"]) if per_image else None,
         "roofline": {"bound": "alu", "achieved": fit_tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": fit_tfs / VALU_PEAK_TFLOPS,

@@ -373,6 +373,31 @@ itc_status itc_lattice_label_batched(itc_plan* p, const void* weights, const voi
 /* Number of images in the plan, or -1 for NULL. */
 int32_t itc_lattice_plan_size(const itc_plan* p);
 
+/*
+ * Tile shapes of a plan's convolution (the batched form of Section 3.1's
+ * convolutions), for autotuning. The convolution runs one persistent launch
+ * per radius class over that class's tiles: 64-column strips cut into
+ * segments of about `seg_rows` rows, with `blocks_per_cu` workgroups per
+ * compute unit. The maps do not depend on the shape (bitwise).
+ *
+ * itc_lattice_plan_conv_classes: number of classes, -1 if p is NULL.
+ * itc_lattice_plan_conv_class: class c's key (stable identifier), current
+ *   segment rows and workgroups per compute unit, and the most workgroups per
+ *   compute unit the kernel's resources allow; any output pointer may be NULL.
+ *   ITC_E_NULL for a NULL plan, ITC_E_ARG for c out of range.
+ * itc_lattice_plan_set_conv_shape: sets the class with key `key` to
+ *   `seg_rows` (64..4096, rounded up to a multiple of 16 per image; 0 = the
+ *   default 256) and `blocks_per_cu` (1..the maximum; 0 = the maximum), and
+ *   rebuilds and uploads its tile list (synchronous). ITC_E_ARG for an
+ *   unknown key or out-of-range values. Plan set-up, not a per-call
+ *   operation: no call on the plan may be in flight, and a graph captured
+ *   before the change keeps the old launch shapes, so capture after tuning.
+ */
+int32_t itc_lattice_plan_conv_classes(const itc_plan* p);
+itc_status itc_lattice_plan_conv_class(const itc_plan* p, int32_t c, int32_t* key, int32_t* seg_rows,
+                                       int32_t* blocks_per_cu, int32_t* max_blocks_per_cu);
+itc_status itc_lattice_plan_set_conv_shape(itc_plan* p, int32_t key, int32_t seg_rows, int32_t blocks_per_cu);
+
 /* Frees the plan's device descriptors (after the work using them is done). NULL is a no-op. */
 void itc_lattice_plan_destroy(itc_plan* p);
 

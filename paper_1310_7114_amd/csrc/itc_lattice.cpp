@@ -146,6 +146,10 @@ struct itc_plan {
   // tile list grouped by radius class: [begin, end) per class
   std::vector<ConvTile> tiles;
   std::vector<int> cls, cls_begin, cls_end, cls_grid;
+  // convolution tile shape per class key (set by the autotuning hook; 0 =
+  // default): target segment rows and workgroups per compute unit
+  std::vector<int> key_seg, key_per;
+  size_t tile_cap = 0;  // capacity of d_tiles (the most tiles any shape gives)
   std::vector<int32_t> order;  // fit order, most expensive first
   int fit_grid = 1;
   std::vector<itc::GradTile> gtiles;  // 64 x 64 tiles of every image, for dL/dh
@@ -164,6 +168,62 @@ struct itc_plan {
   itc::ChamferTask* d_ch_cols = nullptr;
   itc::ChamferTask* d_ch_rows = nullptr;
 };
+
+// Convolution tile lists of a plan: per class key (the VALU kernel's radius
+// class, or CONV_MX_CLASS + aligned radius for the matrix-core kernel), every
+// image's strips cut into segments of about the class's target height
+// (multiples of the chunk height), sorted by cost, most expensive first; one
+// persistent launch per class with the class's workgroups per compute unit.
+constexpr int PLAN_NKEYS = itc::CONV_MX_CLASS + 33;
+constexpr int PLAN_SEG_DEFAULT = 256, PLAN_SEG_MIN = 64, PLAN_SEG_MAX = 4096;
+
+static int class_key_of(const ImageDesc& im) {
+  return itc::conv_uses_mx(false, im.wdtype) ? itc::CONV_MX_CLASS + itc::conv_mx_radius(im.rclass) : im.rclass;
+}
+
+static int class_occupancy(int key) {
+  const int per = itc::conv_tiles_blocks_per_cu(false, key);
+  return per < 1 ? 1 : per;
+}
+
+static void build_conv_tiles(itc_plan* p) {
+  std::vector<std::vector<ConvTile>> by_class(PLAN_NKEYS);
+  std::vector<std::vector<int64_t>> cost_of(PLAN_NKEYS);
+  for (int i = 0; i < p->n; ++i) {
+    const ImageDesc& im = p->images[i];
+    const int key = class_key_of(im), rc = im.rclass;
+    const int target = p->key_seg[key] > 0 ? p->key_seg[key] : PLAN_SEG_DEFAULT;
+    int nseg = (im.H + target - 1) / target;
+    int S = (im.H + nseg - 1) / nseg;
+    S = (S + itc::CONV_CH - 1) / itc::CONV_CH * itc::CONV_CH;
+    nseg = (im.H + S - 1) / S;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int rows = std::min(S, im.H - sg * S);
+      for (int st2 = 0; st2 < im.nstrips; ++st2) {
+        by_class[key].push_back(ConvTile{i, st2, sg * S, S});
+        cost_of[key].push_back((int64_t)(rows + 2 * rc) * (2 * rc + 1));
+      }
+    }
+  }
+  p->tiles.clear();
+  p->cls.clear();
+  p->cls_begin.clear();
+  p->cls_end.clear();
+  p->cls_grid.clear();
+  const int cus = device_cus();
+  for (int key = 0; key < PLAN_NKEYS; ++key) {
+    if (by_class[key].empty()) continue;
+    std::vector<int> idx(by_class[key].size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cost_of[key][a] > cost_of[key][c]; });
+    p->cls.push_back(key);
+    p->cls_begin.push_back((int)p->tiles.size());
+    for (int k : idx) p->tiles.push_back(by_class[key][k]);
+    p->cls_end.push_back((int)p->tiles.size());
+    const int per = p->key_per[key] > 0 ? p->key_per[key] : class_occupancy(key);
+    p->cls_grid.push_back(std::min(p->cls_end.back() - p->cls_begin.back(), per * cus));
+  }
+}
 
 extern "C" {
 
@@ -320,9 +380,6 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   p->images.resize(b->n);
   // class keys: the VALU kernel's radius class, or CONV_MX_CLASS + aligned
   // radius for the matrix-core kernel (8-bit weights)
-  constexpr int NKEYS = itc::CONV_MX_CLASS + 33;
-  std::vector<std::vector<ConvTile>> by_class(NKEYS);
-  std::vector<std::vector<int64_t>> cost_of(NKEYS);
   std::vector<double> fit_cost(b->n);
   for (int i = 0; i < b->n; ++i) {
     int R = 0, rc = 0;
@@ -358,19 +415,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     p->images[i] = im;
     p->m_max = std::max(p->m_max, im.M);
     p->max_passes = std::max(p->max_passes, itc::fit_passes_of(im.M));
-    // tiles: segments of at most ~256 rows, multiples of the chunk height
-    int nseg = (im.H + 255) / 256;
-    int S = (im.H + nseg - 1) / nseg;
-    S = (S + itc::CONV_CH - 1) / itc::CONV_CH * itc::CONV_CH;
-    nseg = (im.H + S - 1) / S;
-    const int key = itc::conv_uses_mx(false, im.wdtype) ? itc::CONV_MX_CLASS + itc::conv_mx_radius(rc) : rc;
-    for (int sg = 0; sg < nseg; ++sg) {
-      const int rows = std::min(S, im.H - sg * S);
-      for (int st2 = 0; st2 < im.nstrips; ++st2) {
-        by_class[key].push_back(ConvTile{i, st2, sg * S, S});
-        cost_of[key].push_back((int64_t)(rows + 2 * rc) * (2 * rc + 1));
-      }
-    }
+    p->tile_cap += (size_t)im.nstrips * (size_t)((im.H + PLAN_SEG_MIN - 1) / PLAN_SEG_MIN);
     fit_cost[i] = (double)(im.iters + 1) * im.M * (im.M + 16.0);
     for (int u0 = 0; u0 < im.H; u0 += 64)
       for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
@@ -381,26 +426,14 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     // row groups shared by the chamfer row pass and the labelling (equal heights, checked below)
     for (int r0 = 0; r0 < im.H; r0 += itc::chamfer_rows_per_task()) p->ch_rows.push_back(itc::ChamferTask{i, r0});
   }
-  for (int rc = 0; rc < NKEYS; ++rc) {
-    if (by_class[rc].empty()) continue;
-    std::vector<int> idx(by_class[rc].size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cost_of[rc][a] > cost_of[rc][c]; });
-    p->cls.push_back(rc);
-    p->cls_begin.push_back((int)p->tiles.size());
-    for (int k : idx) p->tiles.push_back(by_class[rc][k]);
-    p->cls_end.push_back((int)p->tiles.size());
-  }
+  p->key_seg.assign(PLAN_NKEYS, 0);
+  p->key_per.assign(PLAN_NKEYS, 0);
+  build_conv_tiles(p);
   p->order.resize(b->n);
   std::iota(p->order.begin(), p->order.end(), 0);
   std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int c) { return fit_cost[a] > fit_cost[c]; });
 
   const int cus = device_cus();
-  for (size_t c = 0; c < p->cls.size(); ++c) {
-    int per = itc::conv_tiles_blocks_per_cu(false, p->cls[c]);
-    if (per < 1) per = 1;
-    p->cls_grid.push_back(std::min(p->cls_end[c] - p->cls_begin[c], per * cus));
-  }
   int fper = itc::fit_blocks_per_cu(false, p->m_max, p->max_passes);
   if (fper < 1) fper = 1;
   p->fit_grid = std::min(p->n, fper * cus);
@@ -408,7 +441,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   p->sx_grid = std::min((int)p->sxblocks.size(), 8 * cus);
 
   hipError_t e = hipMalloc(&p->d_images, sizeof(ImageDesc) * p->n);
-  if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tiles.size()));
+  if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tile_cap));
   if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int32_t) * p->n);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_images, p->images.data(), sizeof(ImageDesc) * p->n, hipMemcpyHostToDevice);
@@ -439,6 +472,38 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
 }
 
 int32_t itc_lattice_plan_size(const itc_plan* p) { return p ? p->n : -1; }
+
+int32_t itc_lattice_plan_conv_classes(const itc_plan* p) { return p ? (int32_t)p->cls.size() : -1; }
+
+itc_status itc_lattice_plan_conv_class(const itc_plan* p, int32_t c, int32_t* key, int32_t* seg_rows,
+                                       int32_t* blocks_per_cu, int32_t* max_blocks_per_cu) {
+  if (!p) return fail(ITC_E_NULL, "plan is NULL");
+  if (c < 0 || c >= (int32_t)p->cls.size())
+    return fail(ITC_E_ARG, "class index %d outside [0, %d)", c, (int)p->cls.size());
+  const int k = p->cls[c];
+  if (key) *key = k;
+  if (seg_rows) *seg_rows = p->key_seg[k] > 0 ? p->key_seg[k] : PLAN_SEG_DEFAULT;
+  if (blocks_per_cu) *blocks_per_cu = p->key_per[k] > 0 ? p->key_per[k] : class_occupancy(k);
+  if (max_blocks_per_cu) *max_blocks_per_cu = class_occupancy(k);
+  return ok();
+}
+
+itc_status itc_lattice_plan_set_conv_shape(itc_plan* p, int32_t key, int32_t seg_rows, int32_t blocks_per_cu) {
+  if (!p) return fail(ITC_E_NULL, "plan is NULL");
+  if (std::find(p->cls.begin(), p->cls.end(), key) == p->cls.end())
+    return fail(ITC_E_ARG, "class key %d is not a convolution class of this plan", key);
+  if (seg_rows != 0 && (seg_rows < PLAN_SEG_MIN || seg_rows > PLAN_SEG_MAX))
+    return fail(ITC_E_ARG, "segment rows %d outside [%d, %d]", seg_rows, PLAN_SEG_MIN, PLAN_SEG_MAX);
+  if (blocks_per_cu < 0 || blocks_per_cu > class_occupancy(key))
+    return fail(ITC_E_ARG, "workgroups per compute unit %d outside [0, %d]", blocks_per_cu, class_occupancy(key));
+  p->key_seg[key] = seg_rows;
+  p->key_per[key] = blocks_per_cu;
+  build_conv_tiles(p);
+  if (p->tiles.size() > p->tile_cap) return fail(ITC_E_DEVICE, "tile list exceeds its capacity");
+  hipError_t e = hipMemcpy(p->d_tiles, p->tiles.data(), sizeof(ConvTile) * p->tiles.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(e, "tile upload");
+  return ok();
+}
 
 itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps, const double* s_x, const void* w,
                                                    const double* grad_d, void* grad_w, void* grad_weights,

@@ -86,6 +86,9 @@ SIGNATURES = {
                                                ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
+    "itc_lattice_plan_conv_classes": (ctypes.c_int32, [_P]),
+    "itc_lattice_plan_conv_class": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "itc_lattice_plan_set_conv_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "itc_lattice_plan_destroy": (None, [_P]),
     "itc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "itc_last_error": (ctypes.c_char_p, []),
@@ -489,6 +492,21 @@ class BatchPlan:
         if w is None:
             raise ValueError("this plan holds no weights: pass them")
         return w
+
+    def conv_classes(self):
+        """Convolution classes of the plan: [{key, seg_rows, blocks_per_cu, max_blocks_per_cu}]."""
+        lib = load()
+        out = []
+        for c in range(lib.itc_lattice_plan_conv_classes(self.handle)):
+            v = [ctypes.c_int32() for _ in range(4)]
+            _check(lib.itc_lattice_plan_conv_class(self.handle, c, *[ctypes.byref(x) for x in v]))
+            out.append(dict(zip(("key", "seg_rows", "blocks_per_cu", "max_blocks_per_cu"), (x.value for x in v))))
+        return out
+
+    def set_conv_shape(self, key: int, seg_rows: int = 0, blocks_per_cu: int = 0):
+        """Tile shape of one convolution class (0 = default); capture graphs after this."""
+        torch.cuda.synchronize()
+        _check(load().itc_lattice_plan_set_conv_shape(self.handle, int(key), int(seg_rows), int(blocks_per_cu)))
 
     def precompute(self, weights=None, maps=None):
         _check(load().itc_lattice_precompute_batched(self.handle, _ptr(self._w(weights)),

@@ -104,6 +104,10 @@ def test_null_and_range_arguments(itc):
     assert lib.itc_lattice_fit_batched(None, P, P, -1.0, P, None, None, None, None) == 1
     assert lib.itc_lattice_plan_size(None) == -1
     lib.itc_lattice_plan_destroy(None)
+    # autotuning hooks of the convolution's tile shapes
+    assert lib.itc_lattice_plan_conv_classes(None) == -1
+    assert lib.itc_lattice_plan_conv_class(None, 0, None, None, None, None) == 1
+    assert lib.itc_lattice_plan_set_conv_shape(None, 0, 256, 0) == 1
 
 
 def test_chamfer_arguments(itc):
