@@ -299,9 +299,24 @@ def gpu_extras(dev, cases, itc, synth):
     work = torch.empty(1 << 26, dtype=torch.uint8, device=dev)
     t20 = timed(lambda: itc.fit_literal(x2, w02, xi2, om2, 20, work=work), reps=3)
     t0 = timed(lambda: itc.fit_literal(x2, w02, xi2, om2, 0, work=work), reps=3)
+    # the same calls replayed from HIP graphs (no host enqueue cost per launch)
+    graphs = {}
+    for k in (20, 0):
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            itc.fit_literal(x2, w02, xi2, om2, k, work=work)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graphs[k] = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graphs[k]):
+            itc.fit_literal(x2, w02, xi2, om2, k, work=work)
+    g20 = timed(graphs[20].replay, reps=5)
+    g0 = timed(graphs[0].replay, reps=5)
     out["literal_shapes512"] = {"xi": xi2, "omega": om2, "M": c2.M, "sweeps": 20, "ms_total": t20 * 1e3,
-                                "ms_per_sweep": (t20 - t0) / 20 * 1e3, "ms_setup": t0 * 1e3}
-    del work
+                                "ms_per_sweep": (t20 - t0) / 20 * 1e3, "ms_setup": t0 * 1e3,
+                                "graph_ms_total": g20 * 1e3, "graph_ms_per_sweep": (g20 - g0) / 20 * 1e3}
+    del work, graphs
 
     # maps by recursive filtering: cost per pixel independent of sigma
     c4 = synth.config4_case(0)
@@ -350,6 +365,8 @@ def parse():
                    help="launch on the stream instead of replaying a HIP graph (for counter profiling)")
     p.add_argument("--no-tune", action="store_true",
                    help="keep the default convolution tile shapes instead of autotuning them")
+    p.add_argument("--tune-cache", default=None,
+                   help="JSON cache of tuned shapes (default: $ITC_TUNE_CACHE or ~/.cache/itc_lattice/tune.json)")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     return p.parse_args()
@@ -398,7 +415,7 @@ def main():
     tuned = None
     if not args.no_tune:
         from paper_1310_7114_amd import autotune
-        tuned = {str(k): v for k, v in autotune.tune_conv(plan).items()}
+        tuned = {str(k): v for k, v in autotune.tune_conv(plan, path=args.tune_cache).items()}
         print(f"[bench] autotuned convolution shapes {tuned}", file=sys.stderr, flush=True)
     w = torch.empty_like(w0)
     sx = torch.empty(n, dtype=torch.float64, device=dev)

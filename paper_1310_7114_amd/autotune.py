@@ -76,7 +76,8 @@ def tune_conv(plan, seg_candidates: Sequence[int] = SEG_CANDIDATES, reps: int = 
     Call before capturing graphs of the plan."""
     path = cache_path(path)
     store = _load(path) if use_cache else {}
-    dev = torch.cuda.get_device_name()
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    dev = f"{getattr(props, 'gcnArchName', props.name)}|cus={props.multi_processor_count}"
     sig = batch_signature(plan)
     chosen: Dict[int, dict] = {}
     changed = False
