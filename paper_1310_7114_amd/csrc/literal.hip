@@ -15,7 +15,7 @@
 // Then c = V(X;W)/V(W), w_k^new = (b_k - c d_k + c e_k w_k)/a_k, rounded to
 // the nearest lattice point (halves upward) and clamped into the lattice.
 //
-// One sweep is two launches: a wave per codevector for the four sums
+// One sweep is two launches: a workgroup per codevector for the four sums
 // (FP64 accumulation), then one workgroup for the entropies, D, the update
 // and the stopping test. A state word lets the launches after convergence
 // return at once, so the host can enqueue every sweep up front.
@@ -26,6 +26,7 @@ namespace itc {
 namespace {
 
 constexpr int LIT_NT = 256;
+constexpr int LIT_MAXR = 256;  // largest window radius of G_omega the host accepts
 
 __device__ __forceinline__ double gtap(const double* g, int t) { return g[t < 0 ? -t : t]; }
 
@@ -88,35 +89,72 @@ __global__ void __launch_bounds__(LIT_NT) literal_vx_kernel(LiteralArgs la) {
   if (threadIdx.x == 0) la.vx_part[blockIdx.x] = s;
 }
 
-// The four window sums of codevector k = blockIdx.x (one wave).
-__global__ void __launch_bounds__(64) literal_terms_kernel(LiteralArgs la, const int32_t* __restrict__ w) {
+// The four window sums of codevector k = blockIdx.x, one workgroup: lanes
+// along v, the four waves taking every fourth window row, lanes along j for
+// the codebook overlaps; each sum is reduced per wave by a fixed DPP tree and
+// then over the waves in order.
+__global__ void __launch_bounds__(LIT_NT) literal_terms_kernel(LiteralArgs la, const int32_t* __restrict__ w) {
+  __shared__ double red[6][LIT_NT / 64];
+  __shared__ double tap_s[3 * LIT_MAXR + 2];  // g [R + 1], then the overlaps [2R + 1]
   if (*la.state >= 2) return;
-  const int k = blockIdx.x, lane = threadIdx.x;
-  const double* g = la.taps;
-  const double* k1 = la.taps + (la.R + 1);
+  const int k = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = LIT_NT / 64;
+  for (int t = threadIdx.x; t < 3 * la.R + 2; t += LIT_NT) tap_s[t] = la.taps[t];
+  __syncthreads();
+  const double* g = tap_s;
+  const double* k1 = tap_s + (la.R + 1);
   const int wu = w[2 * k], wv = w[2 * k + 1];
   const int R = la.R;
   const int u0 = max(wu - R, 0), u1 = min(wu + R, la.H - 1);
   const int v0 = max(wv - R, 0), v1 = min(wv + R, la.W - 1);
-  // data: a, b over the window (lanes along v)
+  // data: a, b over the window. A lane takes two columns 64 apart; each step
+  // of a wave takes four of its rows, all eight loads issued before use
+  // (rows past the window load the last row and weigh 0).
   double a = 0.0, bu = 0.0, bv = 0.0;
-  for (int vb = v0; vb <= v1; vb += 64) {
-    const int v = vb + lane;
-    if (v > v1) break;
-    const double fv = gtap(g, v - wv);
-    double ca = 0.0, cu = 0.0;
-    for (int u = u0; u <= u1; ++u) {
-      const double pf = (double)la.P[(int64_t)u * la.ppitch + v] * gtap(g, u - wu);
-      ca += pf;
-      cu = fma((double)u, pf, cu);
+  for (int vb = v0; vb <= v1; vb += 128) {
+    int vc[2];
+    bool okc[2];
+    double fv[2], ca[2] = {0.0, 0.0}, cu[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      vc[h] = vb + 64 * h + lane;
+      okc[h] = vc[h] <= v1;
+      vc[h] = okc[h] ? vc[h] : v1;
+      fv[h] = okc[h] ? gtap(g, vc[h] - wv) : 0.0;
     }
-    a = fma(fv, ca, a);
-    bu = fma(fv, cu, bu);
-    bv = fma(fv * (double)v, ca, bv);
+    for (int ub = u0 + wave; ub <= u1; ub += 4 * NW) {
+      float pv[4][2];
+      double gu[4];
+      int uu[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int u = ub + r * NW;
+        uu[r] = u <= u1 ? u : u1;
+        gu[r] = u <= u1 ? gtap(g, u - wu) : 0.0;
+        const float* row = la.P + (int64_t)uu[r] * la.ppitch;
+        pv[r][0] = row[vc[0]];
+        pv[r][1] = row[vc[1]];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double pf = (double)pv[r][h] * gu[r];
+          ca[h] += pf;
+          cu[h] = fma((double)uu[r], pf, cu[h]);
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a = fma(fv[h], ca[h], a);
+      bu = fma(fv[h], cu[h], bu);
+      bv = fma(fv[h] * (double)vc[h], ca[h], bv);
+    }
   }
-  // codebook: e, d over the other codevectors' overlapping windows (lanes along j)
+  // codebook: e, d over the other codevectors' overlapping windows (threads along j)
   double e = 0.0, du = 0.0, dv = 0.0;
-  for (int j = lane; j < la.M; j += 64) {
+  for (int j = threadIdx.x; j < la.M; j += LIT_NT) {
     double Ku, K1u, Kv, K1v;
     overlap1d(w[2 * j], wu, la.H, R, g, k1, Ku, K1u);
     if (Ku == 0.0) continue;
@@ -125,20 +163,17 @@ __global__ void __launch_bounds__(64) literal_terms_kernel(LiteralArgs la, const
     du = fma(K1u, Kv, du);
     dv = fma(Ku, K1v, dv);
   }
-  a = wave_sum(a);
-  bu = wave_sum(bu);
-  bv = wave_sum(bv);
-  e = wave_sum(e);
-  du = wave_sum(du);
-  dv = wave_sum(dv);
+  const double part[6] = {wave_sum(a), wave_sum(bu), wave_sum(bv), wave_sum(e), wave_sum(du), wave_sum(dv)};
   if (lane == 0) {
-    double* t = la.terms + 6 * k;
-    t[0] = a;
-    t[1] = bu;
-    t[2] = bv;
-    t[3] = e;
-    t[4] = du;
-    t[5] = dv;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red[q][wave] = part[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) s += red[threadIdx.x][ww];
+    la.terms[6 * k + threadIdx.x] = s;
   }
 }
 
@@ -196,10 +231,11 @@ __global__ void __launch_bounds__(LIT_NT) literal_update_kernel(LiteralArgs la, 
 }  // namespace
 
 hipError_t launch_literal(const LiteralArgs& la, const int32_t* w_init, int32_t* w_out, hipStream_t s) {
+  if (la.R < 1 || la.R > LIT_MAXR) return hipErrorInvalidValue;
   hipLaunchKernelGGL(literal_setup_kernel, dim3(1), dim3(LIT_NT), 0, s, la, w_init, w_out);
   hipLaunchKernelGGL(literal_vx_kernel, dim3(la.nvx), dim3(LIT_NT), 0, s, la);
   for (int t = 0; t <= la.iters; ++t) {
-    hipLaunchKernelGGL(literal_terms_kernel, dim3(la.M), dim3(64), 0, s, la, (const int32_t*)w_out);
+    hipLaunchKernelGGL(literal_terms_kernel, dim3(la.M), dim3(LIT_NT), 0, s, la, (const int32_t*)w_out);
     hipLaunchKernelGGL(literal_update_kernel, dim3(1), dim3(LIT_NT), 0, s, la, w_out, t);
   }
   return hipGetLastError();
