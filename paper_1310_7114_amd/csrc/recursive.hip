@@ -136,21 +136,35 @@ __global__ void __launch_bounds__(64) rec_seg_scan_kernel(double* __restrict__ Z
   if (c >= cols) return;
   const double* P = rc.P;
   double z1 = 0.0, z2 = 0.0, z3 = 0.0;
-  for (int i = 0; i < nseg; ++i) {
-    const int sg = dir > 0 ? i : nseg - 1 - i;
-    double* e1 = zat(Z, sg, 0, cols, c);
-    double* e2 = zat(Z, sg, 1, cols, c);
-    double* e3 = zat(Z, sg, 2, cols, c);
-    const double f1 = *e1, f2 = *e2, f3 = *e3;
-    *e1 = z1;
-    *e2 = z2;
-    *e3 = z3;
-    const double n1 = fma(P[0], z1, fma(P[1], z2, fma(P[2], z3, f1)));
-    const double n2 = fma(P[3], z1, fma(P[4], z2, fma(P[5], z3, f2)));
-    const double n3 = fma(P[6], z1, fma(P[7], z2, fma(P[8], z3, f3)));
-    z1 = n1;
-    z2 = n2;
-    z3 = n3;
+  constexpr int SB = 8;  // segments whose ends are loaded together
+  for (int i0 = 0; i0 < nseg; i0 += SB) {
+    double f[SB][3];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int i = i0 + q;
+      const int sg = dir > 0 ? i : nseg - 1 - i;
+      f[q][0] = f[q][1] = f[q][2] = 0.0;
+      if (i < nseg) {
+        f[q][0] = *zat(Z, sg, 0, cols, c);
+        f[q][1] = *zat(Z, sg, 1, cols, c);
+        f[q][2] = *zat(Z, sg, 2, cols, c);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int i = i0 + q;
+      if (i >= nseg) break;
+      const int sg = dir > 0 ? i : nseg - 1 - i;
+      *zat(Z, sg, 0, cols, c) = z1;
+      *zat(Z, sg, 1, cols, c) = z2;
+      *zat(Z, sg, 2, cols, c) = z3;
+      const double n1 = fma(P[0], z1, fma(P[1], z2, fma(P[2], z3, f[q][0])));
+      const double n2 = fma(P[3], z1, fma(P[4], z2, fma(P[5], z3, f[q][1])));
+      const double n3 = fma(P[6], z1, fma(P[7], z2, fma(P[8], z3, f[q][2])));
+      z1 = n1;
+      z2 = n2;
+      z3 = n3;
+    }
   }
 }
 

@@ -11,6 +11,8 @@ reports the traffic figure.
 
     python3 -m paper_1310_7114_amd.profsummary --trace T --fetch F --write W \
         --calib-mib 1024 --commands commands.txt --out profiles
+    python3 -m paper_1310_7114_amd.profsummary --secondary --trace T2 \
+        --commands commands2.txt --out profiles
 """
 from __future__ import annotations
 
@@ -80,15 +82,57 @@ def copy_kernel_value(per, expected_kib: float):
     return best
 
 
+# secondary workloads of the benchmark's extras: summary name -> (title, kernel name fragments)
+SECONDARY = {
+    "volume_96x192x256": ("3-D lattice maps and fit: 96 x 192 x 256 ellipsoid volume, sigma 2, M 64, 50 sweeps",
+                          ["vol_"]),
+    "literal_shapes512": ("Algorithm 1 on the 512 x 512 shapes with the paper's widths (M 100, 20 and 0 sweeps)",
+                          ["literal_"]),
+    "recursive_gray2048": ("recursive Gaussian maps of the 2048 x 2048 gray image, sigma 4, 16 and 40",
+                           ["rec_"]),
+    "chamfer_silhouettes1400": ("chamfer transform of the 1400 silhouettes (batched)", ["chamfer_"]),
+    "segments_silhouettes1400": ("nearest-codevector labels of the 1400 silhouettes (batched)", ["label_"]),
+}
+
+
+def secondary(trace: str, commands: str, out: str) -> None:
+    """Kernel-duration tables of the secondary workloads from one kernel-trace run of bench.py with extras."""
+    stats = kernel_stats(trace)
+    cmds = open(commands).read().strip()
+    os.makedirs(out, exist_ok=True)
+    for name, (title, frags) in SECONDARY.items():
+        names = sorted(k for k in stats if any(f in k for f in frags))
+        if not names:
+            continue
+        lines = [f"# {name}", "", f"{title}; kernel durations (rocprofv3 --kernel-trace --stats) from the",
+                 "benchmark's secondary measurements, every launch of the run. Produced by these commands, from",
+                 "the repository root:", "", "```", cmds, "```", "",
+                 "| kernel | calls | average us | total us |", "|---|---|---|---|"]
+        for k in names:
+            c, avg, tot = stats[k]
+            lines.append(f"| {k} | {c} | {avg:.1f} | {tot:.1f} |")
+        path = os.path.join(out, f"{name}.md")
+        with open(path, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print("wrote", path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--calib-mib", type=float, required=True)
+    ap.add_argument("--secondary", action="store_true",
+                    help="write the secondary workloads' kernel tables from --trace (no counter runs)")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--calib-mib", type=float)
     ap.add_argument("--commands", required=True, help="text file with the commands that produced the runs")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
+    if a.secondary:
+        secondary(a.trace, a.commands, a.out)
+        return
+    if not (a.fetch and a.write and a.calib_mib):
+        ap.error("--fetch, --write and --calib-mib are required without --secondary")
 
     stats = kernel_stats(a.trace)
     fetch = counters(a.fetch, "FETCH_SIZE")
