@@ -65,6 +65,38 @@ def test_tuned_plan_gives_the_default_results(gpu_lib, tmp_path):
            {k: (v["seg_rows"], v["blocks_per_cu"]) for k, v in chosen.items()}
 
 
+def test_graph_captured_after_tuning_replays_exactly(gpu_lib, tmp_path):
+    """A graph captured after tuning equals eager execution on every replay
+    (with eager work and synchronisation between the replays)."""
+    cases = S.config3_cases(indices=range(5, 1400, 20))
+    plan, w0 = make_plan(gpu_lib, cases)
+    n = plan.n
+    T.tune_conv(plan, reps=2, path=str(tmp_path / "tune.json"))
+    w = torch.empty_like(w0)
+    sx = torch.empty(n, dtype=torch.float64, device="cuda")
+    d = torch.empty_like(sx)
+    done = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan.run(w0, w, sx, d, done)
+    torch.cuda.synchronize()
+    ref = (w.clone(), sx.clone(), d.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.run(w0, w, sx, d, done)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(w0, w, sx, d, done)
+    for _ in range(3):
+        w.zero_()
+        d.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(w, ref[0]) and torch.equal(sx, ref[1]) and torch.equal(d, ref[2])
+
+
 def test_bad_shapes_are_rejected(gpu_lib):
     plan, _ = make_plan(gpu_lib, S.config3_cases(indices=range(4)))
     key = plan.conv_classes()[0]["key"]
