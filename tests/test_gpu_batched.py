@@ -51,6 +51,49 @@ def test_batched_equals_per_image_bitwise(gpu_lib):
             assert torch.equal(x, y), i
 
 
+def large_m_cases():
+    """Gray images whose codebooks need two and four passes of the fit
+    (M = 257..1024) beside small ones, several widths."""
+    out = []
+    for i, (M, sigma, H, W) in enumerate([(10, 2.0, 96, 120), (257, 3.0, 160, 200), (300, 4.0, 144, 176),
+                                          (700, 2.0, 200, 240), (1024, 3.0, 224, 256), (64, 4.0, 128, 128)]):
+        img = S.gray_gaussians((9, i), H=H, W=W, n=12, major=(8, 40))
+        w0 = S.sample_init(img, M, (9, i, 1))
+        out.append(S.LatticeCase(img, 1.0 / 255.0, w0, sigma, S.radius_for(sigma), 20, name=f"gray-M{M}"))
+    return out
+
+
+def test_batched_large_codebooks(gpu_lib):
+    """Codebooks of up to 1,024 codevectors in one plan: batched results are
+    bitwise the per-image ones. Against the oracle: M = 300 (two passes)
+    after the 20 sweeps, M = 1,024 (four passes) after one sweep. With 700 or
+    1,024 codevectors on ~5e4 weighted pixels the iteration is unstable
+    (codevectors with almost no data in their window take huge steps), so
+    rounding differences grow about tenfold per sweep from the second on."""
+    cases = large_m_cases()
+    plan, w0 = make_plan(gpu_lib, cases)
+    w, sx, d, done = run_plan(plan, w0)
+    for i, c in enumerate(cases):
+        m = gpu_lib.precompute(torch.from_numpy(c.img).cuda(), c.sigma, scale=c.scale)
+        wi, tr, _ = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda(), c.iters)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.unpack(w, i), wi), c.name
+        assert float(d[i]) == float(tr[-1]), c.name
+        assert int(done[i]) == c.iters
+    c = cases[2]
+    W_ref, tr_ref, _, _ = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters)
+    got = plan.unpack(w, 2).cpu().double().numpy()
+    assert np.linalg.norm(got - W_ref, axis=1).max() <= 1e-3
+    assert abs(float(d[2]) - tr_ref[-1]) <= 1e-5 * max(1.0, abs(tr_ref[-1]))
+    c = cases[4]
+    m = gpu_lib.precompute(torch.from_numpy(c.img).cuda(), c.sigma, scale=c.scale)
+    w1, tr1, _ = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda(), 1)
+    torch.cuda.synchronize()
+    W1, trr1, _, _ = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, 1)
+    assert np.linalg.norm(w1.cpu().double().numpy() - W1, axis=1).max() <= 1e-4
+    assert np.abs(tr1.cpu().numpy() - trr1).max() <= 1e-5 * max(1.0, np.abs(trr1).max())
+
+
 def test_full_batch_sampled_against_oracle(gpu_lib):
     """All 1,400 silhouettes in one plan (the benchmark's launch configuration);
     sampled images are checked against the oracle one by one."""
