@@ -23,8 +23,8 @@ if ROOT not in sys.path:
 
 METRIC = "images/sec to converged codebook (batched vs per-image); conv HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
-# MI355X vector FP32 peak (256 CUs, 2.4 GHz). The build emits no packed FP32
-# instructions, but the chip's unpacked FP32 FMA throughput measures above half
+# MI355X vector FP32 peak (256 CUs, 2.4 GHz). The kernels are compiled without
+# packed FP32 instructions, but the chip's unpacked FP32 FMA throughput measures above half
 # of this figure, so half of it would not bound the kernel.
 VALU_PEAK_TFLOPS = 157.3
 # one ordered codebook pair of a sweep: 2 differences, |d|^2 (mul + fma), exp2,
@@ -375,7 +375,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(images would shard across GPUs with no communication); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
