@@ -437,6 +437,19 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   int fper = itc::fit_blocks_per_cu(false, p->m_max, p->max_passes);
   if (fper < 1) fper = 1;
   p->fit_grid = std::min(p->n, fper * cus);
+  {
+    // Workgroup g fits the images at positions g, g + grid, ...: deal the
+    // cost-sorted images to the positions of each round in alternating
+    // directions, so the most expensive of one round and the cheapest of the
+    // next share a workgroup.
+    const std::vector<int32_t> sorted = p->order;
+    const int grid = p->fit_grid;
+    for (int r0 = 0; r0 < p->n; r0 += grid) {
+      const int cnt = std::min(grid, p->n - r0);
+      const bool rev = (r0 / grid) & 1;
+      for (int q = 0; q < cnt; ++q) p->order[r0 + q] = sorted[r0 + (rev ? cnt - 1 - q : q)];
+    }
+  }
   p->grad_grid = std::min((int)p->gtiles.size(), 4 * cus);
   p->sx_grid = std::min((int)p->sxblocks.size(), 8 * cus);
 
