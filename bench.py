@@ -506,8 +506,7 @@ def main():
         maps = [plan.maps_of(i) for i in range(n)]
         ws = [plan.unpack(w0, i) for i in range(n)]
         outs = [plan.unpack(w, i) for i in range(n)]
-        imgs = [plan.weights[int(plan.weight_off[i]): int(plan.weight_off[i]) + cases[i].img.size]
-                .view(cases[i].img.shape) for i in range(n)]
+        imgs = [plan.image(plan.weights, i) for i in range(n)]
         dtr = [torch.empty(c.iters + 1, dtype=torch.float64, device=dev) for c in cases]
         dn = torch.empty(n, dtype=torch.int32, device=dev)
 

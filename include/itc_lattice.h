@@ -97,17 +97,21 @@ typedef struct {
 /* Effective truncation radius of `d` (radius, or ceil(3 sigma) when 0); -1 if invalid. */
 int32_t itc_lattice_radius(const itc_lattice_desc* d);
 
-/* Elements per map row (width rounded up to a multiple of 64); -1 if invalid. */
-int64_t itc_lattice_map_pitch(const itc_lattice_desc* d);
+/*
+ * Elements per map plane: ceil(width/16) panels x height x 16; -1 if
+ * invalid. Each plane is stored in panels of 16 columns: element (u, v)
+ * (row u, column v) is at index ((v / 16) * height + u) * 16 + v % 16, so
+ * a 16 x 16 tile of a plane is one contiguous block (1 KiB in FP32).
+ */
+int64_t itc_lattice_plane_elems(const itc_lattice_desc* d);
 
 /*
- * Bytes of the maps buffer for `d`, 0 if `d` is invalid. Layout (all in the
- * real type): plane A, then plane M_u, then plane M_v, each height x
- * map_pitch row-major; then a library-internal trailer: ceil(width/64) x
- * ceil(height/8) x 64 partial sums of S_X in the real type, and after them
- * (8-byte aligned) ceil(width/64) x ceil(ceil(height/8)/64) FP64 block sums
- * of those partials. The size is a multiple of 256 bytes; the buffer must be
- * 256-byte aligned.
+ * Bytes of the maps buffer for `d`, 0 if `d` is invalid. Layout (planes in
+ * the real type): plane A, then plane M_u, then plane M_v, each
+ * itc_lattice_plane_elems(d) elements in the panel layout above; then, 8-byte
+ * aligned, a library-internal trailer of ceil(width/64) x ceil(height/64) x 4
+ * FP64 partial sums of S_X. The size is a multiple of 256 bytes; the buffer
+ * must be 256-byte aligned.
  */
 size_t itc_lattice_maps_bytes(const itc_lattice_desc* d);
 
@@ -115,7 +119,10 @@ size_t itc_lattice_maps_bytes(const itc_lattice_desc* d);
  * Section 3.1 / Algorithm 1 "compute P once": the convolution maps of the
  * weight image and S_X. `weights` points at the stored image (layout in `d`),
  * `maps` at itc_lattice_maps_bytes(d) bytes (written), `s_x` at one double
- * (written). Map columns beyond `width` inside the pitch get unspecified values.
+ * (written). Map columns beyond `width` inside the last panel get unspecified
+ * values. 8-bit weights whose rows start 4-byte aligned (base and pitch) take
+ * the matrix-core convolution, others the vector-ALU one (same maps to
+ * rounding).
  */
 itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights, void* maps,
                                   double* s_x, void* stream);
@@ -304,7 +311,9 @@ itc_status itc_volume_fit(const itc_volume_desc* d, const void* maps, const doub
  * batch layout; its calls launch one persistent kernel each (convolution
  * over a cost-sorted tile queue; fit over a cost-sorted image queue) and
  * contain no allocation, synchronisation or memset, so they can be captured
- * into a HIP graph. Results are bitwise identical to the per-image calls.
+ * into a HIP graph. Results are bitwise identical to the per-image calls on
+ * the same stored images (the same convolution kernel is chosen when the
+ * per-image weights pointer has the image's alignment).
  * All images must use real_dtype ITC_F32.
  * ------------------------------------------------------------------------ */
 typedef struct itc_plan itc_plan;
@@ -322,7 +331,12 @@ typedef struct {
 /* Validates every image and builds the plan (copies descriptors to the device). */
 itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out);
 
-/* Convolution maps of every image (one persistent launch). */
+/*
+ * Convolution maps and S_X partials of every image: one persistent launch
+ * per radius class. 8-bit images whose weight_off and pitch are multiples of
+ * 4 take the matrix-core convolution; the weights base must then be 4-byte
+ * aligned (ITC_E_ARG otherwise).
+ */
 itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void* maps, void* stream);
 
 /*

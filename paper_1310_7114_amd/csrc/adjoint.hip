@@ -44,7 +44,6 @@ __device__ void grad_weights_tile(const ImageDesc& im, int u0, int v0, const Gra
                                   double gd, GradSmem<T>& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int H = im.H, W = im.W, R = im.R, M = im.M;
-  const int mpl = (int)im.map_pitch;
   const T* Ap = reinterpret_cast<const T*>((const char*)ga.maps + im.map_off);
   const V2<T>* wk = reinterpret_cast<const V2<T>*>(ga.w) + im.w_off;
 
@@ -68,7 +67,7 @@ __device__ void grad_weights_tile(const ImageDesc& im, int u0, int v0, const Gra
         for (int c = 0; c < 4; ++c) {
           const int i = i0 + (c >> 1), j = j0 + (c & 1);
           if (i >= 0 && i < H && j >= 0 && j < W)
-            A = fma_t(((c >> 1) ? fu : (T)1 - fu) * ((c & 1) ? fv : (T)1 - fv), Ap[(size_t)i * mpl + j], A);
+            A = fma_t(((c >> 1) ? fu : (T)1 - fu) * ((c & 1) ? fv : (T)1 - fv), Ap[map_index(H, i, j)], A);
         }
         sxw += (double)A;
         rel = i0 - R <= u0 + GT - 1 && i0 + 1 + R >= u0 && j0 - R <= v0 + GT - 1 && j0 + 1 + R >= v0;
@@ -138,7 +137,7 @@ __device__ void grad_weights_tile(const ImageDesc& im, int u0, int v0, const Gra
     for (int r = 0; r < GROWS; ++r) {
       const int row = u0 + wave * GROWS + r;
       if (row < H) {
-        const T Ay = Ap[(size_t)row * mpl + col];
+        const T Ay = Ap[map_index(H, row, col)];
         g[(size_t)row * W + col] = fma_t(c1, Ay, c2 * K[r]);
       }
     }

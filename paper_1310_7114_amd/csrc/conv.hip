@@ -2,8 +2,8 @@
 // the Parzen sum of delta impulses is the image convolved with a Gaussian; for
 // small widths the 2-D mask factorises into 1-D masks). One pass produces
 //   A   = (I *_v g) *_u g,   M_u = (I *_v g) *_u tg,   M_v = (I *_v tg) *_u g
-// with g[t] = exp(-t^2/(2 sigma^2)), tg[t] = t g[t], |t| <= R, and partial
-// sums of S_X = sum I A (one per lane and 8-row group; summed in FP64 later).
+// with g[t] = exp(-t^2/(2 sigma^2)), tg[t] = t g[t], |t| <= R, and FP64
+// partial sums of S_X = sum I A (one per wave and SX_ROWS-row group).
 //
 // Work decomposition (gfx950): a workgroup of two waves owns a strip of 64
 // columns (lane = column) and a segment of rows, and streams down it in
@@ -18,8 +18,9 @@
 //      8w..8w+7 of the chunk for its lane's column: A, M_u, M_v (24
 //      accumulators). A 16-row block of the ring never wraps, and the block
 //      and offset of every read are compile-time for a given w, so each read
-//      is one base register plus an immediate offset. Outputs are stored
-//      coalesced (lanes = columns); h*A is summed per lane into an S_X partial.
+//      is one base register plus an immediate offset. Outputs are stored in
+//      the maps' panel layout; h*A is summed per lane in FP64 and per wave
+//      into the S_X partial of each SX_ROWS-row group.
 // Two waves per workgroup keep two waves on every SIMD at the LDS budget of
 // one ring, so one wave's LDS, scalar and memory instructions issue beside
 // the other's FMAs. Taps are computed once per segment in FP64 (one lane per
@@ -155,8 +156,7 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
   const int esz = wdtype == 0 ? 1 : (wdtype == 1 ? 4 : 8);
   const uint32_t rowbytes = (uint32_t)(im.pitch * esz);
   const rsrc_t wres = make_rsrc(wbase + im.weight_off, (uint32_t)H * rowbytes);
-  const rsrc_t mres = make_rsrc(mbase + im.map_off, (uint32_t)(im.part_off + (int64_t)im.nstrips * im.ngroups *
-                                                                             CONV_TW * sizeof(T)));
+  const rsrc_t mres = make_rsrc(mbase + im.map_off, (uint32_t)(3 * im.plane * (int64_t)sizeof(T)));
   const T scale = (T)im.scale;
 
   // ---- taps: g[t], tg[t] for t = 0..R (zero beyond the true radius) ----
@@ -223,13 +223,17 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
     });
   };
 
-  const uint32_t mpb = (uint32_t)(im.map_pitch * sizeof(T));     // bytes per map row
-  const uint32_t planeb = (uint32_t)H * mpb;                       // bytes per plane
+  const uint32_t planeb = (uint32_t)(im.plane * (int64_t)sizeof(T));  // bytes per plane
   const int col = v0 + lane;
   const bool col_ok = col < W;
+  const bool col_stored = col < im.npanels * MAP_PANEL;  // the strip may reach past the last panel
   const uint32_t hoff = col_ok ? (uint32_t)col : 0u;
-  const uint32_t mvoff = (uint32_t)col * (uint32_t)sizeof(T);     // inside the padded pitch
-  const uint32_t part_base = (uint32_t)im.part_off + (uint32_t)((int64_t)strip * im.ngroups * CONV_TW * sizeof(T));
+  // byte offset of row 0 of this lane's column in the panel layout; rows are MAP_PANEL elements apart
+  const uint32_t mvoff = (uint32_t)map_index(H, 0, col) * (uint32_t)sizeof(T);
+  constexpr uint32_t rowstep = MAP_PANEL * sizeof(T);
+  double* part = reinterpret_cast<double*>(mbase + im.map_off + im.part_off) +
+                 (int64_t)strip * im.nsxg * SX_SLOTS + 2 * wave;
+  double sxd = 0.0;  // this lane's share of the current S_X row group
 
   const int rq = lane >> 4, cg = lane & 15;  // row pass: row in a set of 4, column group of 4
 
@@ -307,22 +311,33 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
 #pragma unroll
           for (int k = 0; k < KB; ++k) hv[k] = raw_value<T, WT>(hraw[k]);
         });
-        // rows are stored whole: the strip's 64 columns lie inside the padded
-        // map pitch, and columns past the width carry zero weight for S_X
+        // columns past the width inside the last panel are stored too (never
+        // read); they carry zero weight for S_X
         T sx = (T)0;
-        uint32_t so = (uint32_t)o0 * mpb;
+        uint32_t so = (uint32_t)o0 * rowstep;
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
-          if (o0 + k < seg_end) {
+          if (o0 + k < seg_end && col_stored) {
             buf_store<T>(a[k], mres, mvoff, so);
             buf_store<T>(mu[k], mres, mvoff, so + planeb);
             buf_store<T>(mv[k], mres, mvoff, so + 2 * planeb);
-            sx = fma_t(hv[k], a[k], sx);
           }
-          so += mpb;
+          if (o0 + k < seg_end) sx = fma_t(hv[k], a[k], sx);
+          so += rowstep;
         }
-        buf_store<T>(sx * scale, mres, (uint32_t)lane * (uint32_t)sizeof(T),
-                     part_base + (uint32_t)(o0 / KB) * (uint32_t)(CONV_TW * sizeof(T)));
+        sxd += (double)sx;
+      }
+      // the last chunk of an S_X row group (or of the segment): wave w writes
+      // slot 2w of the group's partials and clears slot 2w + 1
+      const int jo = j - G::J0;
+      if ((jo + 1) % (SX_ROWS / CH) == 0 || jo == n_out - 1) {  // uniform
+        const double tot = wave_sum(sxd);
+        const int g = (s0 + jo * CH) / SX_ROWS;
+        if (lane == 0) {
+          part[(int64_t)g * SX_SLOTS] = tot * (double)im.scale;
+          part[(int64_t)g * SX_SLOTS + 1] = 0.0;
+        }
+        sxd = 0.0;
       }
     }
   }
@@ -357,55 +372,12 @@ __global__ void __launch_bounds__(CONV_NT) conv_tiles_kernel(const ImageDesc* __
   }
 }
 
-// S_X = sum over the lattice of h A, from the partials the convolution
-// leaves per strip, 8-row group and lane. First level: block b of an image
-// (strip b / nb, groups SX_GROUPS (b mod nb) ..) is summed in a fixed order
-// into one FP64 value; second level: the block values in order. Both
-// levels depend only on the image shape, so every path gets the same bits.
-template <typename T>
-__device__ __forceinline__ void sx_block_sum(const ImageDesc& im, char* mbase, int b, double* red) {
-  const int nb = sx_blocks_per_strip(im.H);
-  const int strip = b / nb, g0 = (b - strip * nb) * SX_GROUPS;
-  const int ng = min(SX_GROUPS, im.ngroups - g0);
-  const T* part = reinterpret_cast<const T*>(mbase + im.map_off + im.part_off) +
-                  ((int64_t)strip * im.ngroups + g0) * CONV_TW;
-  // thread t adds partials t, t + 256, ... in order; all loads are issued first
-  constexpr int PER = SX_GROUPS * CONV_TW / 256;
-  const int n = ng * CONV_TW;
-  T v[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = (int)threadIdx.x + 256 * k;
-    v[k] = i < n ? part[i] : (T)0;
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) s += (double)v[k];
-  s = block_reduce_fixed(s, red);
-  if (threadIdx.x == 0) reinterpret_cast<double*>(mbase + im.map_off + im.sx_off)[b] = s;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) sx_blocks_kernel(ImageDesc im, char* mbase) {
-  __shared__ double red[4];
-  sx_block_sum<T>(im, mbase, blockIdx.x, red);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) sx_blocks_batched_kernel(const ImageDesc* __restrict__ images,
-                                                                const SxBlock* __restrict__ blocks, int nblocks,
-                                                                char* mbase) {
-  __shared__ double red[4];
-  for (int k = blockIdx.x; k < nblocks; k += gridDim.x) {
-    const SxBlock sb = blocks[k];
-    sx_block_sum<T>(images[sb.img], mbase, sb.b, red);
-  }
-}
-
+// S_X = the sum of an image's FP64 partials, in a fixed order that depends
+// only on the image shape, so every path gets the same bits.
 __global__ void __launch_bounds__(256) sx_total_kernel(ImageDesc im, const char* mbase, double* s_x) {
   __shared__ double red[4];
-  const double* blk = reinterpret_cast<const double*>(mbase + im.map_off + im.sx_off);
-  const double s = block_sum_fixed(blk, (int64_t)im.nstrips * sx_blocks_per_strip(im.H), red);
+  const double* part = reinterpret_cast<const double*>(mbase + im.map_off + im.part_off);
+  const double s = block_sum_fixed(part, (int64_t)im.nstrips * im.nsxg * SX_SLOTS, red);
   if (threadIdx.x == 0) *s_x = s;
 }
 
@@ -416,19 +388,20 @@ __global__ void __launch_bounds__(256) sx_total_kernel(ImageDesc im, const char*
 #define ITC_FOR_CLASSES_F64(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16)
 
 // Segment length for a single image: enough workgroups to fill the chip,
-// but long enough that the 2R-row warm-up of each segment stays small.
+// but long enough that the 2R-row warm-up of each segment stays small; a
+// multiple of SX_ROWS.
 int conv_segment_rows(const ImageDesc& im) {
   const int target = 1024;  // ~4 workgroups per compute unit
   int segs = (target + im.nstrips - 1) / im.nstrips;
   int S = (im.H + segs - 1) / segs;
   const int smin = 4 * im.rclass > 64 ? 4 * im.rclass : 64;
   if (S < smin) S = smin;
-  S = (S + CONV_CH - 1) / CONV_CH * CONV_CH;
+  S = (S + SX_ROWS - 1) / SX_ROWS * SX_ROWS;  // segments start at multiples of the S_X row group
   return S;
 }
 
 hipError_t launch_conv_image(bool f64, const ImageDesc& im, const void* w, void* m, hipStream_t s) {
-  if (conv_uses_mx(f64, im.wdtype)) return launch_conv_mx_image(im, w, m, s);
+  if (conv_uses_mx(f64, im.wdtype, w, im.weight_off, im.pitch)) return launch_conv_mx_image(im, w, m, s);
   const int S = conv_segment_rows(im);
   const dim3 grid(im.nstrips * ((im.H + S - 1) / S));
 #define ITC_CASE_F(RR)                                                                           \
@@ -493,25 +466,8 @@ int conv_tiles_blocks_per_cu(bool f64, int rclass) {
 #undef ITC_CASE_D
 }
 
-hipError_t launch_sx_finalize(bool f64, const ImageDesc& img, const void* maps, double* s_x,
-                              hipStream_t s) {
-  const dim3 grid((unsigned)n_sx_blocks(img.H, img.W));
-  if (f64)
-    hipLaunchKernelGGL(sx_blocks_kernel<double>, grid, dim3(256), 0, s, img, (char*)maps);
-  else
-    hipLaunchKernelGGL(sx_blocks_kernel<float>, grid, dim3(256), 0, s, img, (char*)maps);
+hipError_t launch_sx_finalize(const ImageDesc& img, const void* maps, double* s_x, hipStream_t s) {
   hipLaunchKernelGGL(sx_total_kernel, dim3(1), dim3(256), 0, s, img, (const char*)maps, s_x);
-  return hipGetLastError();
-}
-
-hipError_t launch_sx_blocks_batched(bool f64, const ImageDesc* d_images, const SxBlock* d_blocks, int nblocks,
-                                    void* maps, int grid, hipStream_t s) {
-  if (f64)
-    hipLaunchKernelGGL(sx_blocks_batched_kernel<double>, dim3(grid), dim3(256), 0, s, d_images, d_blocks, nblocks,
-                       (char*)maps);
-  else
-    hipLaunchKernelGGL(sx_blocks_batched_kernel<float>, dim3(grid), dim3(256), 0, s, d_images, d_blocks, nblocks,
-                       (char*)maps);
   return hipGetLastError();
 }
 

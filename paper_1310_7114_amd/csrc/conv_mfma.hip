@@ -3,7 +3,7 @@
 // weight image convolved with a Gaussian, whose mask factorises into 1-D
 // masks). The maps are the same as the VALU kernel's:
 //   A = (I *_v g) *_u g,   M_u = (I *_v g) *_u tg,   M_v = (I *_v tg) *_u g,
-// with f(t) the tap at t = x_out - x_in, plus the S_X partials.
+// with f(t) the tap at t = x_out - x_in, plus the FP64 partials of S_X.
 //
 // Each 1-D pass is a banded Toeplitz product. Sixteen outputs along an axis
 // are a 16 x K window of inputs times the K x 16 matrix T[k][n] = f(n + RA - k)
@@ -16,27 +16,31 @@
 //     R0 = X (g_hi + g_lo) and R1 = X (tg_hi + tg_lo) are exact products
 //     summed in FP32;
 //   - column pass: R0 and R1, scaled by a power of two into FP16 range, are
-//     split y = y_hi + y_lo, and every map is the sum of the four products
-//     T_a y_b, accumulated as a hi chain and a lo chain.
+//     split y = y_hi + y_lo, and every map is T_hi y_hi + T_hi y_lo +
+//     T_lo y_hi; the dropped T_lo y_lo is below 2^-22 of sum |T| |y|.
 // The relative error of a map is a few 2^-22 against an FP32 direct sum's
 // 2^-24 per operation.
 //
 // Work decomposition: a workgroup of four waves owns a strip of 64 columns
-// and a segment of rows and streams down it in chunks of 16 rows. Wave w owns
-// columns 16w..16w+15 in both passes, so the ring that carries row-pass
-// results to the column pass is private to the wave (LDS operations of one
-// wave complete in order: no barrier). Per chunk:
-//   1. staging (shared): the chunk's 16 input rows with their column halo
-//      are converted to FP16 into one of two LDS buffers; their global loads
-//      were issued one chunk earlier. One barrier per chunk.
+// and a segment of rows (starting at a multiple of SX_ROWS) and streams down
+// it in chunks of 16 rows. Wave w owns columns 16w..16w+15 (one map panel) in
+// both passes, so the rings that carry row-pass results to the column pass
+// are private to the wave (LDS operations of one wave complete in order: no
+// barrier). Per chunk:
+//   1. staging (shared): the chunk's 16 input rows with their column halo,
+//      fetched two chunks earlier as aligned 4-byte words, are converted to
+//      FP16 into one of two LDS buffers. One barrier per chunk.
 //   2. row pass: K/32 A-fragments (16 rows x 32 columns) times the tap
 //      fragments -> R0, R1 for 16 rows x 16 columns; scaled, split and
 //      written to the ring (column-major: rows contiguous, so the column
-//      pass reads 8 consecutive rows per lane in one 16-byte load).
-//   3. column pass, 2RA rows behind: ring fragments (K rows x 16 columns)
-//      times the same tap fragments (as the A operand) -> A, M_u, M_v for 16
-//      rows x 16 columns, stored coalesced along rows, and h*A summed into
-//      the S_X partial of each 8-row group.
+//      pass reads 8 consecutive rows per lane in one 16-byte load); the
+//      stored weights of the wave's columns go to a byte ring for S_X.
+//   3. column pass, 2RA rows behind: the ring fragments are the A operand
+//      and the taps the B operand, so the product is the transposed tile and
+//      each lane holds four adjacent columns of one output row. A 16 x 16
+//      tile of a map is then one contiguous 1 KiB of its panel, written by a
+//      single 16-byte-per-lane store; h*A is summed into an FP64 partial of
+//      S_X per SX_ROWS-row group.
 #include <type_traits>
 
 #include "itc_device.h"
@@ -48,9 +52,12 @@ namespace {
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MX_NT = 256;  // four waves; wave w owns strip columns 16w..16w+15
 constexpr int MX_CH = 16;   // rows per chunk
+static_assert(SX_ROWS % MX_CH == 0 && SX_SLOTS == MX_NT / 64, "one S_X slot per wave and row group");
+static_assert(CONV_TW == 4 * MAP_PANEL, "a strip is four panels");
 
 template <int RA>
 struct MxGeom {
@@ -63,16 +70,16 @@ struct MxGeom {
   // (or column) offset each hit 4 distinct banks: pitch/2 = 4 * odd dwords.
   static constexpr int RINGP = NB * MX_CH + 8;   // ring column pitch
   static constexpr int SW = 48 + K;              // staged columns (image columns v0 - RA + c)
+  static constexpr int SWD = SW / 4;             // staged 4-byte words per row
   static constexpr int SWP = SW + 8;             // staged row pitch
-  static constexpr int CC = (SW + 63) / 64;      // staged columns per lane and row
+  static constexpr int NI = (MX_CH * SWD + MX_NT - 1) / MX_NT;  // staged words per thread and chunk
   static constexpr size_t STAGE = (size_t)MX_CH * SWP;     // halves per staging buffer
   static constexpr size_t RINGA = (size_t)CONV_TW * RINGP;  // halves per ring array
-  static constexpr int RINGB = NB * MX_CH + 4;                // h byte ring column pitch (bytes)
-  static constexpr size_t SMEM = (2 * STAGE + 4 * RINGA) * sizeof(_Float16) + (size_t)CONV_TW * RINGB;
+  static constexpr int HROWS = NB * MX_CH;                   // rows of a wave's weight ring (16 bytes each)
+  static constexpr size_t SMEM = (2 * STAGE + 4 * RINGA) * sizeof(_Float16) + (size_t)4 * HROWS * 16;
   static_assert(RINGP / 2 % 8 == 4 && SWP / 2 % 8 == 4, "bank-spread pitches");
   static_assert(NB * MX_CH >= MX_CH + 2 * RA, "ring holds a column window");
-  static_assert(RINGB / 4 % 2 == 1, "bank-spread byte ring");
-static constexpr int MINW = (int)((160 * 1024) / SMEM) < 8 ? (int)((160 * 1024) / SMEM) : 8;
+  static_assert(SW % 4 == 0 && RA % 4 == 0, "word-aligned staging");
 };
 
 __device__ __forceinline__ f4_t mfma(h8_t a, h8_t b, f4_t c) {
@@ -96,7 +103,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
   using G = MxGeom<RA>;
   _Float16* stage = smem;                  // [2][16][SWP]
   _Float16* ring = smem + 2 * G::STAGE;    // [4][64][RINGP]: R0 hi, R0 lo, R1 hi, R1 lo
-  uint8_t* hring = reinterpret_cast<uint8_t*>(ring + 4 * G::RINGA);  // [64][RINGB]: stored weights
+  uint32_t* hring = reinterpret_cast<uint32_t*>(ring + 4 * G::RINGA);  // [4 waves][HROWS][4 words]
 
   // lane-derived values are recomputed per segment: an opaque thread index
   // keeps the compiler from hoisting them out of the persistent tile loop,
@@ -113,10 +120,8 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
   const int nchunks = G::J0 + n_out;
   const int origin = s0 - RA;  // image row of row 0 of chunk 0
 
-  const uint32_t rowbytes = (uint32_t)im.pitch;  // 8-bit weights
-  const rsrc_t wres = make_rsrc(wbase + im.weight_off, (uint32_t)H * rowbytes);
-  const rsrc_t mres = make_rsrc(mbase + im.map_off, (uint32_t)(im.part_off + (int64_t)im.nstrips * im.ngroups *
-                                                                             CONV_TW * sizeof(float)));
+  const int rowbytes = (int)im.pitch;  // 8-bit weights, a multiple of 4
+  const rsrc_t wres = make_rsrc(wbase + im.weight_off, (uint32_t)H * (uint32_t)rowbytes);
 
   // ---- tap fragments: element e of lane (n, q), k-step s holds 2^8 f(t), t = n + RA - (32s + 8q + e) ----
   h8_t g_hi[G::KS], g_lo[G::KS], t_hi[G::KS], t_lo[G::KS];
@@ -153,73 +158,80 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     fac = (float)(im.scale * __builtin_ldexp(1.0, e1 - 16));  // undoes the 2^8 taps twice and sc1
   }
 
-  // ---- staging: wave w loads rows 4w..4w+3 of a chunk, staged columns lane + 64c ----
-  // Lanes past the staged width or outside the image load at an offset past
-  // the end of the buffer: the hardware returns 0 without a memory request.
-  uint32_t xoff[G::CC];
+  // ---- staging: thread item i of a chunk is staged word d of row r ----
+  // (r, d) = divmod(tid + 256 i, SWD); the word holds image columns
+  // v0 - RA + 4d .. +3 (v0 - RA is a multiple of 8, so the word is aligned).
+  // Words left of the image, rows outside it and items past the chunk load
+  // at an offset past the end of the buffer: the hardware returns 0 without
+  // a memory request. Bytes of a word past the width are masked to 0.
+  int irow[G::NI], icol[G::NI], ioff[G::NI];
+  uint32_t imask[G::NI];
 #pragma unroll
-  for (int c = 0; c < G::CC; ++c) {
-    const int sc = lane + 64 * c, x = v0 - RA + sc;
-    xoff[c] = sc < G::SW && x >= 0 && x < W ? (uint32_t)x : 0x80000000u;
+  for (int i = 0; i < G::NI; ++i) {
+    const int idx = tid + MX_NT * i;
+    const int r = idx / G::SWD, d = idx - r * G::SWD;
+    const int x = v0 - RA + 4 * d;
+    const bool item = idx < MX_CH * G::SWD;
+    const bool ok = item && x >= 0 && x < W;
+    const int keep = W - x;  // bytes of the word inside the image
+    irow[i] = ok ? r : -(1 << 20);             // never inside the image: the load reads 0
+    icol[i] = x;
+    ioff[i] = item ? r * G::SWP + 4 * d : -1;  // halves into a staging buffer
+    imask[i] = !ok ? 0u : (keep >= 4 ? 0xffffffffu : (1u << (8 * keep)) - 1u);
   }
-  // Loads are unconditional and rows outside the image are masked at staging
-  // time, a chunk later, so that nothing waits on them in between.
   // Two chunks are in flight: set P = j & 1 holds chunk j from two chunks
   // before it is staged (P is a template constant so the sets stay in
   // registers), which leaves the loads two chunks of work to arrive.
-  uint32_t pre[2][4][G::CC];
-  uint32_t ymask[2] = {0u, 0u};  // bit r: fetched row 4w + r lies inside the image (uniform)
+  uint32_t pre[2][G::NI];
   auto fetch = [&](int j, auto P) {
     constexpr int p = decltype(P)::value;
-    ymask[p] = 0u;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int y = origin + j * MX_CH + 4 * wave + r;  // uniform
-      const bool yin = y >= 0 && y < H;
-      ymask[p] |= yin ? 1u << r : 0u;
-      const uint32_t soff = yin ? (uint32_t)y * rowbytes : 0u;
-#pragma unroll
-      for (int c = 0; c < G::CC; ++c) pre[p][r][c] = buf_load<uint8_t>(wres, xoff[c], soff);
+    for (int i = 0; i < G::NI; ++i) {
+      const int y = origin + j * MX_CH + irow[i];
+      const bool in = y >= 0 && y < H;
+      const uint32_t off = in ? (uint32_t)(y * rowbytes + icol[i]) : 0x80000000u;
+      pre[p][i] = __builtin_amdgcn_raw_buffer_load_b32(wres, off, 0, 0);
     }
   };
-  auto stage_chunk = [&](int j, auto P) {
+  auto stage_chunk = [&](auto P) {
     constexpr int p = decltype(P)::value;
-    _Float16* xs = stage + p * G::STAGE + (4 * wave) * G::SWP + lane;
+    _Float16* xs = stage + p * G::STAGE;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const bool yin = (ymask[p] >> r) & 1u;
-#pragma unroll
-      for (int c = 0; c < G::CC; ++c) {
-        const uint32_t v = yin ? pre[p][r][c] : 0u;
-        if (64 * c + 64 <= G::SW || lane + 64 * c < G::SW) xs[r * G::SWP + 64 * c] = (_Float16)(uint16_t)v;
+    for (int i = 0; i < G::NI; ++i) {
+      if (G::NI * MX_NT == MX_CH * G::SWD || ioff[i] >= 0) {
+        const uint32_t v = pre[p][i] & imask[i];
+        h4_t h;
+        h[0] = (_Float16)(float)(v & 0xffu);
+        h[1] = (_Float16)(float)((v >> 8) & 0xffu);
+        h[2] = (_Float16)(float)((v >> 16) & 0xffu);
+        h[3] = (_Float16)(float)(v >> 24);
+        *reinterpret_cast<h4_t*>(xs + ioff[i]) = h;
       }
     }
   };
 
-  const uint32_t mpb = (uint32_t)(im.map_pitch * sizeof(float));  // bytes per map row
-  const uint32_t planeb = (uint32_t)H * mpb;
-  // one descriptor per plane: the three maps share a byte offset
+  // ---- outputs: wave w writes panel 4 strip + w, a 16 x 16 tile per chunk ----
+  const int npan = im.npanels;
+  const int panel = 4 * strip + wave;
+  const bool pan_ok = panel < npan;  // the strip's last panels may lie past the width
+  const uint32_t planeb = (uint32_t)(im.plane * (int64_t)sizeof(float));
   const char* mimg = mbase + im.map_off;
   const rsrc_t resA = make_rsrc(mimg, planeb), resU = make_rsrc(mimg + planeb, planeb),
                resV = make_rsrc(mimg + 2 * (size_t)planeb, planeb);
-  const int col = v0 + 16 * wave + n;  // this lane's output column (inside the padded pitch)
-  const bool col_ok = col < W;
-  const uint32_t part_base = (uint32_t)im.part_off + (uint32_t)((int64_t)strip * im.ngroups * CONV_TW * sizeof(float));
-  const float hscale = (float)im.scale;
+  // byte offset of row o of this lane's panel and columns 4q..4q+3: (panel H + o) 64 + 16 q
+  const uint32_t pan_base = (uint32_t)panel * (uint32_t)H * 64u + 16u * (uint32_t)q;
+  double* part = reinterpret_cast<double*>(mbase + im.map_off + im.part_off) +
+                 ((int64_t)strip * im.nsxg) * SX_SLOTS + wave;
+  const double hscale = im.scale;
   _Float16* ring_col = ring + (size_t)(16 * wave + n) * G::RINGP;
-
-  // Map stores are unconditional: a row outside the segment gets a byte
-  // offset past the end of its plane, which the hardware discards (the
-  // offset plus three rows stays below 2^32: maps are < 2 GiB). With every
-  // chunk issuing the same memory operations, each wait on a load counts
-  // exactly the stores issued after it.
+  uint32_t* hw = hring + wave * G::HROWS * 4;  // this wave's weight ring: [HROWS][4 words]
   constexpr uint32_t MX_DISCARD = 0x80000000u;
-  uint8_t* hcol = hring + (16 * wave + n) * G::RINGB;
+  double sxd = 0.0;  // this lane's share of the current S_X row group
 
   // One chunk: stage j, row pass j, column pass j - J0 (before the first
   // output chunk its results are discarded).
   auto chunk = [&](int j, auto P) {
-    stage_chunk(j, P);
+    stage_chunk(P);
     __syncthreads();
     fetch(j + 2, P);  // past the last chunk: rows outside the image, masked
 
@@ -235,11 +247,12 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         r0 = mfma(a, g_lo[s], r0);
         r1 = mfma(a, t_lo[s], r1);
       }
-      // stored weights of rows 4q..4q+3 at this lane's column, for S_X
-      const _Float16* xh = stage + decltype(P)::value * G::STAGE + (4 * q) * G::SWP + RA + 16 * wave + n;
+      // stored weights of row n, columns 4q..4q+3 of this wave, for S_X
+      const h4_t xh = *reinterpret_cast<const h4_t*>(stage + decltype(P)::value * G::STAGE + n * G::SWP + RA +
+                                                      16 * wave + 4 * q);
       uint32_t hb = 0u;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) hb |= (uint32_t)(uint16_t)xh[i * G::SWP] << (8 * i);
+      for (int i = 0; i < 4; ++i) hb |= (uint32_t)(float)xh[i] << (8 * i);
       h4_t h0, l0, h1, l1;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -249,13 +262,13 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         h1[i] = b.hi;
         l1[i] = b.lo;
       }
-      const int slot = (j % G::NB) * MX_CH + 4 * q;
-      _Float16* rp = ring_col + slot;
+      const int slot = (j % G::NB) * MX_CH;
+      _Float16* rp = ring_col + slot + 4 * q;
       *reinterpret_cast<h4_t*>(rp) = h0;
       *reinterpret_cast<h4_t*>(rp + G::RINGA) = l0;
       *reinterpret_cast<h4_t*>(rp + 2 * G::RINGA) = h1;
       *reinterpret_cast<h4_t*>(rp + 3 * G::RINGA) = l1;
-      *reinterpret_cast<uint32_t*>(hcol + slot) = hb;
+      hw[(slot + n) * 4 + q] = hb;
     }
     // the column pass reads ring rows this wave has just written: keep the
     // compiler from moving LDS accesses across (the hardware keeps their order)
@@ -277,50 +290,45 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         const h8_t y0l = *reinterpret_cast<const h8_t*>(rp + G::RINGA);
         const h8_t y1h = *reinterpret_cast<const h8_t*>(rp + 2 * G::RINGA);
         const h8_t y1l = *reinterpret_cast<const h8_t*>(rp + 3 * G::RINGA);
-        am = mfma(g_hi[s], y0h, am);
-        um = mfma(t_hi[s], y0h, um);
-        vm = mfma(g_hi[s], y1h, vm);
-        am = mfma(g_hi[s], y0l, am);
-        um = mfma(t_hi[s], y0l, um);
-        vm = mfma(g_hi[s], y1l, vm);
-        am = mfma(g_lo[s], y0h, am);
-        um = mfma(t_lo[s], y0h, um);
-        vm = mfma(g_lo[s], y1h, vm);
-        am = mfma(g_lo[s], y0l, am);
-        um = mfma(t_lo[s], y0l, um);
-        vm = mfma(g_lo[s], y1l, vm);
+        am = mfma(y0h, g_hi[s], am);
+        um = mfma(y0h, t_hi[s], um);
+        vm = mfma(y1h, g_hi[s], vm);
+        am = mfma(y0l, g_hi[s], am);
+        um = mfma(y0l, t_hi[s], um);
+        vm = mfma(y1l, g_hi[s], vm);
+        am = mfma(y0h, g_lo[s], am);
+        um = mfma(y0h, t_lo[s], um);
+        vm = mfma(y1h, g_lo[s], vm);
       }
-      // stored weights of output rows o0 + 4q .. +3: window rows RA + 4q .. +3
-      // (block jo + (RA + 4q)/16, offset (RA + 4q) mod 16)
-      const int hq = RA + 4 * q;
+      // lane (n, q) holds row o0 + n, columns 16 wave + 4q + i. Its stored
+      // weights are in the weight ring at window row RA + n (block
+      // jo + (RA + n)/16, row (RA + n) mod 16).
+      const int wr = RA + n;
       const int hb0 = (j + 1 + RA / MX_CH) % G::NB, hb1 = (j + 2 + RA / MX_CH) % G::NB;  // uniform
-      const int hblk = (RA % MX_CH + 4 * q) >= MX_CH ? hb1 : hb0;
-      const uint32_t hb = *reinterpret_cast<const uint32_t*>(hcol + hblk * MX_CH + hq % MX_CH);
-      // rows outside the segment (warm-up chunks, the tail of the last one)
-      // are discarded; interior chunks skip the per-row tests
-      const bool full = jo >= 0 && o0 + MX_CH <= seg_end;  // uniform
-      const uint32_t off0 = (uint32_t)(o0 + 4 * q) * mpb + (uint32_t)col * (uint32_t)sizeof(float);
+      const int hblk = (RA % MX_CH + n) >= MX_CH ? hb1 : hb0;
+      const uint32_t hb = hw[(hblk * MX_CH + wr % MX_CH) * 4 + q];
+      const int row = o0 + n;
+      const bool ok = row >= s0 && row < seg_end;  // warm-up chunks and the tail of the last one
+      const uint32_t off = ok && pan_ok ? pan_base + (uint32_t)row * 64u : MX_DISCARD;
+      f4_t a4, u4, v4;
       float sx = 0.f;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = o0 + 4 * q + i;
-        const bool ok = full || (row >= s0 && row < seg_end);
-        const uint32_t off = ok ? off0 + (uint32_t)i * mpb : MX_DISCARD;
-        const float a = am[i] * fac;
-        buf_store<float>(a, resA, off, 0u);
-        buf_store<float>(um[i] * fac, resU, off, 0u);
-        buf_store<float>(vm[i] * fac, resV, off, 0u);
-        const float h = ok ? (float)((hb >> (8 * i)) & 0xffu) : 0.f;  // zero past the width
-        sx = __builtin_fmaf(h, a, sx);
+        a4[i] = am[i] * fac;
+        u4[i] = um[i] * fac;
+        v4[i] = vm[i] * fac;
+        sx = __builtin_fmaf((float)((hb >> (8 * i)) & 0xffu), a4[i], sx);  // zero past the width
       }
-      // rows 8p..8p+7 of the chunk are lanes q = 2p and 2p + 1
-      sx += __shfl_xor(sx, 16);
-      const int grow = o0 + 8 * (q >> 1);
-      const uint32_t poff = (q & 1) == 0 && grow >= s0 && grow < seg_end
-                                ? part_base + (uint32_t)((grow / CONV_GROUP) * CONV_TW + 16 * wave + n) *
-                                                  (uint32_t)sizeof(float)
-                                : MX_DISCARD;
-      buf_store<float>(sx * hscale, mres, poff, 0u);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, a4), resA, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, u4), resU, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v4), resV, off, 0, 0);
+      sxd += ok ? (double)sx : 0.0;
+      // the last chunk of an S_X row group (or of the segment): one FP64 partial per wave
+      if (jo >= 0 && ((jo + 1) % (SX_ROWS / MX_CH) == 0 || jo == n_out - 1)) {  // uniform
+        const double tot = wave_sum(sxd);
+        if (lane == 0) part[(int64_t)(o0 / SX_ROWS) * SX_SLOTS] = tot * hscale;
+        sxd = 0.0;
+      }
     }
   };
 
@@ -344,7 +352,7 @@ template <int RA>
 __device__ __forceinline__ void mx_clear_rings(_Float16* smem) {
   using G = MxGeom<RA>;
   uint32_t* p = reinterpret_cast<uint32_t*>(smem + 2 * G::STAGE);
-  constexpr int nwords = (int)((4 * G::RINGA * sizeof(_Float16) + (size_t)CONV_TW * G::RINGB) / 4);
+  constexpr int nwords = (int)((4 * G::RINGA * sizeof(_Float16) + (size_t)4 * G::HROWS * 16) / 4);
   for (int i = threadIdx.x; i < nwords; i += MX_NT) p[i] = 0u;
   __syncthreads();
 }

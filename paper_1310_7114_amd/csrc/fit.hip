@@ -112,8 +112,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   __syncthreads();
 
   const int H = im.H, W = im.W;
-  const int mpl = (int)im.map_pitch;
-  const uint32_t planeb = (uint32_t)H * (uint32_t)mpl * (uint32_t)sizeof(T);
+  const uint32_t planeb = (uint32_t)(im.plane * (int64_t)sizeof(T));
   const rsrc_t mres = make_rsrc(a.mbase + im.map_off, 3u * planeb);
   const bool need_d = a.d_trace != nullptr || a.d_out != nullptr;
   // corner values of the cell each owned codevector was last read in (key -2: none yet)
@@ -161,12 +160,11 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
             cell[ps] = key;
             const bool r0 = inside && i0 >= 0, r1 = inside && i0 + 1 < H;
             const bool c0 = j0 >= 0, c1 = j0 + 1 < W;
-            const uint32_t base = (uint32_t)(i0 * mpl + j0) * (uint32_t)sizeof(T);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
               const int di = c >> 1, dj = c & 1;
               const bool ok = (di ? r1 : r0) && (dj ? c1 : c0);
-              const uint32_t off = ok ? base + (uint32_t)(di * mpl + dj) * (uint32_t)sizeof(T) : FIT_OOB;
+              const uint32_t off = ok ? (uint32_t)map_index(H, i0 + di, j0 + dj) * (uint32_t)sizeof(T) : FIT_OOB;
               cav[ps][c] = buf_load<T>(mres, off, 0);
               cmu[ps][c] = buf_load<T>(mres, off, planeb);
               cmv[ps][c] = buf_load<T>(mres, off, 2 * planeb);
@@ -372,10 +370,10 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
   for (int ii = blockIdx.x; ii < fa.n; ii += gridDim.x) {
     const int i = order[ii];
     const ImageDesc im = images[i];
-    // S_X from the block sums of its partials, written with the maps
-    const double* sxb = reinterpret_cast<const double*>((const char*)fa.maps + im.map_off + im.sx_off);
+    // S_X: the fixed-order sum of the FP64 partials written with the maps
+    const double* sxp = reinterpret_cast<const double*>((const char*)fa.maps + im.map_off + im.part_off);
     const double s_x =
-        fa.s_x_in ? fa.s_x_in[i] : block_sum_fixed(sxb, (int64_t)im.nstrips * sx_blocks_per_strip(im.H), red);
+        fa.s_x_in ? fa.s_x_in[i] : block_sum_fixed(sxp, (int64_t)im.nstrips * im.nsxg * SX_SLOTS, red);
     if (threadIdx.x == 0 && fa.s_x_out) fa.s_x_out[i] = s_x;
     FitImageArgs a;
     a.mbase = (const char*)fa.maps;

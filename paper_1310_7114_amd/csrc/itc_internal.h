@@ -15,7 +15,6 @@ constexpr int CONV_CH = 16;     // rows per chunk
 constexpr int CONV_WAVES = 2;   // waves per workgroup, sharing one strip
 constexpr int CONV_NT = 64 * CONV_WAVES;
 constexpr int CONV_KB = CONV_CH / CONV_WAVES;  // output rows per lane per chunk
-constexpr int CONV_GROUP = CONV_KB;            // rows per S_X partial
 constexpr int ITC_MAX_CODEVECTORS_DEV = 1024;
 constexpr int MAX_RADIUS = 32;
 
@@ -35,26 +34,34 @@ inline int radius_class(int R, bool f64) {
   return -1;
 }
 
-inline int64_t map_pitch_of(int W) { return ((int64_t)W + 63) / 64 * 64; }
+// Map planes are stored in panels of MAP_PANEL columns: panel p holds
+// columns MAP_PANEL p .. MAP_PANEL p + MAP_PANEL - 1 of every row, row after
+// row, so a 16 x 16 output tile is one contiguous 1 KiB (FP32) block. Element
+// (u, v) of a plane sits at map_index(H, u, v).
+constexpr int MAP_PANEL = 16;
+__host__ __device__ inline int n_panels(int W) { return (W + MAP_PANEL - 1) / MAP_PANEL; }
+__host__ __device__ inline int64_t plane_elems_of(int H, int W) { return (int64_t)n_panels(W) * H * MAP_PANEL; }
+__host__ __device__ inline int64_t map_index(int H, int u, int v) {
+  return ((int64_t)(v / MAP_PANEL) * H + u) * MAP_PANEL + (v % MAP_PANEL);
+}
 __host__ __device__ inline int n_strips(int W) { return (W + CONV_TW - 1) / CONV_TW; }
-__host__ __device__ inline int n_groups(int H) { return (H + CONV_GROUP - 1) / CONV_GROUP; }
-// S_X partials: one per (strip, CONV_GROUP-row group, lane), in the real type.
-inline int64_t n_partials(int H, int W) { return (int64_t)n_strips(W) * n_groups(H) * CONV_TW; }
-// S_X in two fixed-order levels: block b of an image sums the partials of
-// SX_GROUPS consecutive groups of one strip into one FP64 value (stored after
-// the partials); S_X is the fixed-order sum of those values.
-constexpr int SX_GROUPS = 64;
-__host__ __device__ inline int sx_blocks_per_strip(int H) { return (n_groups(H) + SX_GROUPS - 1) / SX_GROUPS; }
-__host__ __device__ inline int64_t n_sx_blocks(int H, int W) { return (int64_t)n_strips(W) * sx_blocks_per_strip(H); }
+// S_X = sum of FP64 partials, one per (strip, SX_ROWS-row group, slot); a
+// convolution segment starts at a multiple of SX_ROWS, so every partial is
+// written by exactly one workgroup, and S_X is their sum in a fixed order.
+constexpr int SX_ROWS = 64;
+constexpr int SX_SLOTS = 4;
+__host__ __device__ inline int n_sx_groups(int H) { return (H + SX_ROWS - 1) / SX_ROWS; }
+__host__ __device__ inline int64_t n_sx_partials(int H, int W) {
+  return (int64_t)n_strips(W) * n_sx_groups(H) * SX_SLOTS;
+}
 
 // One image as the kernels see it. Offsets are in bytes from the batch bases.
 struct ImageDesc {
   int64_t weight_off;   // stored weights of this image
   int64_t pitch;        // weight row pitch, elements
   int64_t map_off;      // maps of this image (planes A, Mu, Mv, then partials)
-  int64_t map_pitch;    // elements per map row
-  int64_t part_off;     // byte offset of the S_X partials inside the maps
-  int64_t sx_off;       // byte offset of the FP64 block sums of the partials
+  int64_t plane;        // elements per map plane (panels x H x MAP_PANEL)
+  int64_t part_off;     // byte offset of the FP64 S_X partials inside the maps
   int64_t w_off;        // codebook offset, codevectors
   double scale;         // h = scale * stored
   double sigma;
@@ -65,7 +72,8 @@ struct ImageDesc {
   int32_t M;
   int32_t iters;
   int32_t nstrips;
-  int32_t ngroups;
+  int32_t npanels;
+  int32_t nsxg;         // S_X row groups
   int32_t pad_;
 };
 
@@ -81,7 +89,11 @@ struct ConvTile {
 // convolution (8-bit weights, FP32 maps) with aligned radius
 // class - CONV_MX_CLASS (a multiple of 8).
 constexpr int CONV_MX_CLASS = 64;
-inline bool conv_uses_mx(bool f64, int wdtype) { return !f64 && wdtype == 0; }
+// The matrix-core kernel stages rows with 4-byte loads, so every row of the
+// 8-bit image must start 4-byte aligned (image base and pitch).
+inline bool conv_uses_mx(bool f64, int wdtype, const void* wbase, int64_t weight_off, int64_t pitch) {
+  return !f64 && wdtype == 0 && ((uintptr_t)wbase + (uint64_t)weight_off) % 4 == 0 && pitch % 4 == 0;
+}
 int conv_mx_radius(int rclass);
 
 // Launchers (defined in the .hip files). All return hipError_t of the launch.
@@ -100,14 +112,8 @@ hipError_t launch_conv_mx_image(const ImageDesc& h_image, const void* weights, v
 hipError_t launch_conv_mx_tiles(int ra, const ImageDesc* d_images, const ConvTile* d_tiles, int ntiles,
                                 const void* weights, void* maps, int grid, hipStream_t s);
 int conv_mx_blocks_per_cu(int ra);
-hipError_t launch_sx_finalize(bool f64, const ImageDesc& img, const void* maps, double* s_x,
-                              hipStream_t s);
-// Block sums of the S_X partials of many images: one (image, block) pair
-// per entry of `blocks`.
-struct SxBlock {
-  int32_t img;
-  int32_t b;
-};
+// S_X of one image: the fixed-order sum of its FP64 partials.
+hipError_t launch_sx_finalize(const ImageDesc& img, const void* maps, double* s_x, hipStream_t s);
 // 3-D lattices: one volume (slice, row, column) and its window radius.
 struct VolumeGeom {
   int32_t D, H, W, R;
@@ -138,8 +144,7 @@ hipError_t launch_recursive(const ImageDesc& im, const void* x, double scale, do
 // Algorithm 1 (eq. (6) on the lattice): device pointers into the caller's
 // work buffer and the sweep parameters.
 struct LiteralArgs {
-  const float* P;   // A plane of the maps with sigma = xi
-  int64_t ppitch;   // elements per P row
+  const float* P;   // A plane of the maps with sigma = xi (panel layout)
   int32_t H, W, M;
   int32_t R;        // window radius of G_omega
   int32_t iters;
@@ -170,8 +175,6 @@ hipError_t launch_label(bool f64, const ImageDesc& im, const void* x, const void
                         hipStream_t s);
 hipError_t launch_label_batched(const ImageDesc* d_images, const ChamferTask* d_tasks, int ntasks, int m_max,
                                 const void* x, const void* w, int32_t* lab, int grid, hipStream_t s);
-hipError_t launch_sx_blocks_batched(bool f64, const ImageDesc* d_images, const SxBlock* d_blocks, int nblocks,
-                                    void* maps, int grid, hipStream_t s);
 
 struct FitArgs {
   const void* maps;      // batch base of maps

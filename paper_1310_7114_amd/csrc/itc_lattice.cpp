@@ -79,9 +79,8 @@ itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out, bool n
   // the kernels address one image and its maps with 32-bit byte offsets
   const uint64_t esz = d->weight_dtype == ITC_U8 ? 1 : (d->weight_dtype == ITC_F32 ? 4 : 8);
   const uint64_t img_bytes = (uint64_t)d->height * (uint64_t)d->pitch * esz;
-  const uint64_t map_bytes = (uint64_t)3 * d->height * (uint64_t)itc::map_pitch_of(d->width) * (f64 ? 8 : 4) +
-                             (uint64_t)itc::n_partials(d->height, d->width) * (f64 ? 8 : 4) + 8 +
-                             (uint64_t)itc::n_sx_blocks(d->height, d->width) * 8;
+  const uint64_t map_bytes = (uint64_t)3 * (uint64_t)itc::plane_elems_of(d->height, d->width) * (f64 ? 8 : 4) +
+                             (uint64_t)itc::n_sx_partials(d->height, d->width) * 8 + 256;
   if (img_bytes >= (1ull << 31) || map_bytes >= (1ull << 31))
     return fail(ITC_E_UNSUPPORTED, "image (%llu B) or maps (%llu B) exceed 2 GiB", (unsigned long long)img_bytes,
                 (unsigned long long)map_bytes);
@@ -91,26 +90,22 @@ itc_status check_desc(const itc_lattice_desc* d, int* R_out, int* rc_out, bool n
 }
 
 size_t planes_bytes(const itc_lattice_desc& d) {
-  return (size_t)3 * d.height * itc::map_pitch_of(d.width) * real_size(d.real_dtype);
+  return (size_t)3 * (size_t)itc::plane_elems_of(d.height, d.width) * real_size(d.real_dtype);
 }
 
-// FP64 block sums of the S_X partials follow the partials, 8-byte aligned.
-size_t sx_offset(const itc_lattice_desc& d) {
-  const size_t part = (size_t)itc::n_partials(d.height, d.width) * real_size(d.real_dtype);
-  return (planes_bytes(d) + part + 7) / 8 * 8;
-}
+// The FP64 S_X partials follow the planes, 8-byte aligned.
+size_t part_offset(const itc_lattice_desc& d) { return (planes_bytes(d) + 7) / 8 * 8; }
 
 size_t maps_bytes_of(const itc_lattice_desc& d) {
-  return (sx_offset(d) + (size_t)itc::n_sx_blocks(d.height, d.width) * sizeof(double) + 255) / 256 * 256;
+  return (part_offset(d) + (size_t)itc::n_sx_partials(d.height, d.width) * sizeof(double) + 255) / 256 * 256;
 }
 
 ImageDesc make_image(const itc_lattice_desc& d, int R, int rc) {
   ImageDesc im;
   std::memset(&im, 0, sizeof im);
   im.pitch = d.pitch;
-  im.map_pitch = itc::map_pitch_of(d.width);
-  im.part_off = (int64_t)planes_bytes(d);
-  im.sx_off = (int64_t)sx_offset(d);
+  im.plane = itc::plane_elems_of(d.height, d.width);
+  im.part_off = (int64_t)part_offset(d);
   im.scale = d.weight_scale;
   im.sigma = d.sigma;
   im.H = d.height;
@@ -119,7 +114,8 @@ ImageDesc make_image(const itc_lattice_desc& d, int R, int rc) {
   im.rclass = rc;
   im.wdtype = d.weight_dtype;
   im.nstrips = itc::n_strips(d.width);
-  im.ngroups = itc::n_groups(d.height);
+  im.npanels = itc::n_panels(d.width);
+  im.nsxg = itc::n_sx_groups(d.height);
   return im;
 }
 
@@ -158,9 +154,7 @@ struct itc_plan {
   ConvTile* d_tiles = nullptr;
   int32_t* d_order = nullptr;
   itc::GradTile* d_gtiles = nullptr;
-  std::vector<itc::SxBlock> sxblocks;  // S_X block sums of every image
-  int sx_grid = 1;
-  itc::SxBlock* d_sxblocks = nullptr;
+  bool any_mx = false;  // some image runs the matrix-core convolution (4-byte aligned weights base)
   // chamfer transform: column-pass strips and row-pass row groups
   std::vector<itc::ChamferTask> ch_cols, ch_rows;
   bool all_u8 = true;
@@ -172,13 +166,17 @@ struct itc_plan {
 // Convolution tile lists of a plan: per class key (the VALU kernel's radius
 // class, or CONV_MX_CLASS + aligned radius for the matrix-core kernel), every
 // image's strips cut into segments of about the class's target height
-// (multiples of the chunk height), sorted by cost, most expensive first; one
+// (multiples of the S_X row group), sorted by cost, most expensive first; one
 // persistent launch per class with the class's workgroups per compute unit.
 constexpr int PLAN_NKEYS = itc::CONV_MX_CLASS + 33;
 constexpr int PLAN_SEG_DEFAULT = 256, PLAN_SEG_MIN = 64, PLAN_SEG_MAX = 4096;
 
+// The matrix-core kernel needs 4-byte aligned rows: a plan checks the image
+// offsets and pitches here and the weights base at every call.
 static int class_key_of(const ImageDesc& im) {
-  return itc::conv_uses_mx(false, im.wdtype) ? itc::CONV_MX_CLASS + itc::conv_mx_radius(im.rclass) : im.rclass;
+  return itc::conv_uses_mx(false, im.wdtype, nullptr, im.weight_off, im.pitch)
+             ? itc::CONV_MX_CLASS + itc::conv_mx_radius(im.rclass)
+             : im.rclass;
 }
 
 static int class_occupancy(int key) {
@@ -195,7 +193,7 @@ static void build_conv_tiles(itc_plan* p) {
     const int target = p->key_seg[key] > 0 ? p->key_seg[key] : PLAN_SEG_DEFAULT;
     int nseg = (im.H + target - 1) / target;
     int S = (im.H + nseg - 1) / nseg;
-    S = (S + itc::CONV_CH - 1) / itc::CONV_CH * itc::CONV_CH;
+    S = (S + itc::SX_ROWS - 1) / itc::SX_ROWS * itc::SX_ROWS;
     nseg = (im.H + S - 1) / S;
     for (int sg = 0; sg < nseg; ++sg) {
       const int rows = std::min(S, im.H - sg * S);
@@ -246,9 +244,9 @@ int32_t itc_lattice_radius(const itc_lattice_desc* d) {
   return R;
 }
 
-int64_t itc_lattice_map_pitch(const itc_lattice_desc* d) {
+int64_t itc_lattice_plane_elems(const itc_lattice_desc* d) {
   if (check_desc(d, nullptr, nullptr) != ITC_OK) return -1;
-  return itc::map_pitch_of(d->width);
+  return itc::plane_elems_of(d->height, d->width);
 }
 
 size_t itc_lattice_maps_bytes(const itc_lattice_desc* d) {
@@ -268,7 +266,7 @@ itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = itc::launch_conv_image(f64, im, weights, maps, s);
   if (e != hipSuccess) return device_fail(e, "convolution launch");
-  e = itc::launch_sx_finalize(f64, im, maps, s_x, s);
+  e = itc::launch_sx_finalize(im, maps, s_x, s);
   if (e != hipSuccess) return device_fail(e, "S_X launch");
   return ok();
 }
@@ -419,7 +417,6 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     fit_cost[i] = (double)(im.iters + 1) * im.M * (im.M + 16.0);
     for (int u0 = 0; u0 < im.H; u0 += 64)
       for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
-    for (int64_t sb = 0; sb < itc::n_sx_blocks(im.H, im.W); ++sb) p->sxblocks.push_back(itc::SxBlock{i, (int32_t)sb});
     p->all_u8 = p->all_u8 && im.wdtype == ITC_U8;
     p->w_max = std::max(p->w_max, im.W);
     for (int st2 = 0; st2 < im.nstrips; ++st2) p->ch_cols.push_back(itc::ChamferTask{i, st2});
@@ -451,7 +448,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
     }
   }
   p->grad_grid = std::min((int)p->gtiles.size(), 4 * cus);
-  p->sx_grid = std::min((int)p->sxblocks.size(), 8 * cus);
+  for (const ImageDesc& im : p->images) p->any_mx = p->any_mx || class_key_of(im) >= itc::CONV_MX_CLASS;
 
   hipError_t e = hipMalloc(&p->d_images, sizeof(ImageDesc) * p->n);
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tile_cap));
@@ -471,10 +468,6 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   if (e == hipSuccess) e = hipMalloc(&p->d_ch_rows, sizeof(itc::ChamferTask) * p->ch_rows.size());
   if (e == hipSuccess)
     e = hipMemcpy(p->d_ch_rows, p->ch_rows.data(), sizeof(itc::ChamferTask) * p->ch_rows.size(),
-                  hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&p->d_sxblocks, sizeof(itc::SxBlock) * p->sxblocks.size());
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_sxblocks, p->sxblocks.data(), sizeof(itc::SxBlock) * p->sxblocks.size(),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     itc_lattice_plan_destroy(p);
@@ -562,7 +555,6 @@ void itc_lattice_plan_destroy(itc_plan* p) {
   if (p->d_tiles) (void)hipFree(p->d_tiles);
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_gtiles) (void)hipFree(p->d_gtiles);
-  if (p->d_sxblocks) (void)hipFree(p->d_sxblocks);
   if (p->d_ch_cols) (void)hipFree(p->d_ch_cols);
   if (p->d_ch_rows) (void)hipFree(p->d_ch_rows);
   delete p;
@@ -571,15 +563,14 @@ void itc_lattice_plan_destroy(itc_plan* p) {
 itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void* maps, void* stream) {
   if (!p || !weights || !maps) return fail(ITC_E_NULL, "plan, weights and maps must be non-NULL");
   if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
+  if (p->any_mx && (uintptr_t)weights % 4 != 0)
+    return fail(ITC_E_ARG, "8-bit weights must be 4-byte aligned (the images' offsets and pitches are)");
   for (size_t c = 0; c < p->cls.size(); ++c) {
     hipError_t e = itc::launch_conv_tiles(false, p->cls[c], p->d_images, p->d_tiles + p->cls_begin[c],
                                           p->cls_end[c] - p->cls_begin[c], weights, maps, p->cls_grid[c],
                                           (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "batched convolution launch");
   }
-  hipError_t e = itc::launch_sx_blocks_batched(false, p->d_images, p->d_sxblocks, (int)p->sxblocks.size(), maps,
-                                               p->sx_grid, (hipStream_t)stream);
-  if (e != hipSuccess) return device_fail(e, "S_X block sums launch");
   return ok();
 }
 
@@ -665,7 +656,6 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
   itc::LiteralArgs la;
   std::memset(&la, 0, sizeof la);
   la.P = reinterpret_cast<const float*>(wb + L.maps);
-  la.ppitch = im.map_pitch;
   la.H = d->height;
   la.W = d->width;
   la.M = M;
@@ -792,7 +782,7 @@ itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const voi
   double* Z = (double*)((char*)E2 + rec_e2_bytes(*d, c.m));
   hipError_t e = itc::launch_recursive(im, weights, d->weight_scale, d->sigma, c, E1, E2, Z, maps, s);
   if (e != hipSuccess) return device_fail(e, "recursive maps launch");
-  e = itc::launch_sx_finalize(false, im, maps, s_x, s);
+  e = itc::launch_sx_finalize(im, maps, s_x, s);
   if (e != hipSuccess) return device_fail(e, "S_X launch");
   return ok();
 }

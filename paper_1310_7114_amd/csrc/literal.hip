@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(LIT_NT) literal_vx_kernel(LiteralArgs la) {
   const int n = (r1 - r0) * la.W;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int u = r0 + i / la.W, v = i - (i / la.W) * la.W;
-    const double p = (double)la.P[(int64_t)u * la.ppitch + v];
+    const double p = (double)la.P[map_index(la.H, u, v)];
     s = fma(p, p, s);
   }
   s = block_reduce_fixed(s, red);
@@ -131,9 +131,8 @@ __global__ void __launch_bounds__(LIT_NT) literal_terms_kernel(LiteralArgs la, c
         const int u = ub + r * NW;
         uu[r] = u <= u1 ? u : u1;
         gu[r] = u <= u1 ? gtap(g, u - wu) : 0.0;
-        const float* row = la.P + (int64_t)uu[r] * la.ppitch;
-        pv[r][0] = row[vc[0]];
-        pv[r][1] = row[vc[1]];
+        pv[r][0] = la.P[map_index(la.H, uu[r], vc[0])];
+        pv[r][1] = la.P[map_index(la.H, uu[r], vc[1])];
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {

@@ -200,39 +200,47 @@ void rec_filter(double* E, int64_t p, int rows, int cols, const RecCoeffs& rc, d
   hipLaunchKernelGGL(rec_seg_apply_kernel, g, b, 0, s, E, p, rows, cols, rc, -1, Z);
 }
 
-// Maps (FP32 planes, map pitch) and S_X partials from the filtered E2:
-// thread = (8-row group, map column).
+// Maps (FP32 planes, panel layout) and the FP64 S_X partials from the
+// filtered E2: a block of 64 threads takes one panel (16 columns) of one
+// S_X row group, lane (c, r) = (lane mod 16, lane / 16) columns c and rows
+// r, r + 4, ... of it. Panels past the width (the last strip's) only clear
+// their partial slot; columns past the width inside the last panel are 0.
 template <typename WT>
 __global__ void __launch_bounds__(64) rec_maps_kernel(const double* __restrict__ E2, int64_t p2, const WT* x,
                                                       int64_t pitch, double scale, double sigma, ImageDesc im,
                                                       char* maps) {
-  const int v = blockIdx.x * 64 + threadIdx.x;  // map column (< map_pitch)
-  const int grp = blockIdx.y;
-  const int64_t plane = (int64_t)im.H * im.map_pitch;
+  const int panel = blockIdx.x, grp = blockIdx.y;
+  const int lane = threadIdx.x, c = lane & 15, r = lane >> 4;
+  const int v = panel * MAP_PANEL + c;
   float* A = reinterpret_cast<float*>(maps);
-  float* Mu = A + plane;
-  float* Mv = Mu + plane;
+  float* Mu = A + im.plane;
+  float* Mv = Mu + im.plane;
   const double k = -0.5 * sigma * sigma;
   double sx = 0.0;
-  for (int i = 0; i < CONV_GROUP; ++i) {
-    const int u = grp * CONV_GROUP + i;
-    if (u >= im.H) break;
-    float a = 0.f, mu = 0.f, mv = 0.f;
-    if (v < im.W) {
-      const double* e = E2 + (int64_t)(u + 1) * p2 + (v + 1);
-      const double ac = e[0];
-      a = (float)ac;
-      mu = (float)(k * (e[p2] - e[-p2]));
-      mv = (float)(k * (e[1] - e[-1]));
-      sx = fma(scale * (double)x[(int64_t)u * pitch + v], (double)a, sx);
+  if (panel < im.npanels) {
+    for (int i = 0; i < SX_ROWS / 4; ++i) {
+      const int u = grp * SX_ROWS + r + 4 * i;
+      if (u >= im.H) break;
+      float a = 0.f, mu = 0.f, mv = 0.f;
+      if (v < im.W) {
+        const double* e = E2 + (int64_t)(u + 1) * p2 + (v + 1);
+        const double ac = e[0];
+        a = (float)ac;
+        mu = (float)(k * (e[p2] - e[-p2]));
+        mv = (float)(k * (e[1] - e[-1]));
+        sx = fma(scale * (double)x[(int64_t)u * pitch + v], (double)a, sx);
+      }
+      const int64_t o = map_index(im.H, u, v);
+      A[o] = a;
+      Mu[o] = mu;
+      Mv[o] = mv;
     }
-    const int64_t o = (int64_t)u * im.map_pitch + v;
-    A[o] = a;
-    Mu[o] = mu;
-    Mv[o] = mv;
   }
-  float* part = reinterpret_cast<float*>(maps + im.part_off);
-  part[((int64_t)(v / CONV_TW) * im.ngroups + grp) * CONV_TW + (v % CONV_TW)] = (float)sx;
+  sx = wave_sum(sx);
+  if (lane == 0) {
+    double* part = reinterpret_cast<double*>(maps + im.part_off);
+    part[((int64_t)(panel / 4) * im.nsxg + grp) * SX_SLOTS + panel % 4] = sx;
+  }
 }
 
 template <typename WT>
@@ -248,7 +256,8 @@ hipError_t launch_recursive_t(const ImageDesc& im, const void* x, double scale, 
   hipLaunchKernelGGL(rec_transpose_kernel, dim3((cols2 + RT - 1) / RT, (rows2 + RT - 1) / RT), dim3(RT * 8), 0, s,
                      (const double*)E1, p1, H, W, E2, p2, rows2);
   rec_filter(E2, p2, rows2, cols2, rc, Z, s);
-  hipLaunchKernelGGL(rec_maps_kernel<WT>, dim3((unsigned)(im.map_pitch / 64), (unsigned)im.ngroups), dim3(64), 0,
+  static_assert(SX_SLOTS * MAP_PANEL == CONV_TW, "four panels per strip");
+  hipLaunchKernelGGL(rec_maps_kernel<WT>, dim3((unsigned)(im.nstrips * SX_SLOTS), (unsigned)im.nsxg), dim3(64), 0,
                      s, (const double*)E2, p2, (const WT*)x, im.pitch, scale, sigma, im, (char*)maps);
   return hipGetLastError();
 }

@@ -58,7 +58,7 @@ _DP = ctypes.POINTER(Desc)
 # name -> (restype, argtypes)
 SIGNATURES = {
     "itc_lattice_radius": (ctypes.c_int32, [_DP]),
-    "itc_lattice_map_pitch": (ctypes.c_int64, [_DP]),
+    "itc_lattice_plane_elems": (ctypes.c_int64, [_DP]),
     "itc_lattice_maps_bytes": (ctypes.c_size_t, [_DP]),
     "itc_lattice_precompute": (ctypes.c_int, [_DP, _P, _P, _P, _P]),
     "itc_lattice_fit": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
@@ -150,8 +150,19 @@ def maps_bytes(desc: Desc) -> int:
     return int(n)
 
 
-def map_pitch(desc: Desc) -> int:
-    return int(load().itc_lattice_map_pitch(ctypes.byref(desc)))
+def plane_elems(desc: Desc) -> int:
+    return int(load().itc_lattice_plane_elems(ctypes.byref(desc)))
+
+
+MAP_PANEL = 16  # columns per panel of a map plane
+
+
+def panel_view(flat: torch.Tensor, H: int, W: int) -> torch.Tensor:
+    """An (H, W) strided view of one map plane stored in panels of 16 columns
+    (element (u, v) at ((v // 16) * H + u) * 16 + v % 16); the panels are a
+    (panels, H, 16) array, so the view is a permute and reshape (no arithmetic)."""
+    npan = (W + MAP_PANEL - 1) // MAP_PANEL
+    return flat[: npan * H * MAP_PANEL].view(npan, H, MAP_PANEL).permute(1, 0, 2).reshape(H, npan * MAP_PANEL)[:, :W]
 
 
 @dataclass
@@ -163,12 +174,12 @@ class Maps:
     real_dtype: torch.dtype
 
     def planes(self):
-        """(A, M_u, M_v) as (H, W) views of the map buffer."""
+        """(A, M_u, M_v) as (H, W) tensors read out of the panel layout of the map buffer."""
         H, W = self.desc.height, self.desc.width
-        mp = map_pitch(self.desc)
+        n = plane_elems(self.desc)
         esz = torch.finfo(self.real_dtype).bits // 8
-        flat = self.buf[: 3 * H * mp * esz].view(self.real_dtype).view(3, H, mp)
-        return flat[0, :, :W], flat[1, :, :W], flat[2, :, :W]
+        flat = self.buf[: 3 * n * esz].view(self.real_dtype)
+        return tuple(panel_view(flat[i * n:(i + 1) * n], H, W) for i in range(3))
 
 
 def alloc_maps(desc: Desc, device="cuda") -> torch.Tensor:
@@ -378,7 +389,8 @@ class BatchPlan:
 
     def __init__(self, images: Optional[Sequence[torch.Tensor]], ms: Sequence[int], sigmas: Sequence[float],
                  iters: Sequence[int], scales: Optional[Sequence[float]] = None,
-                 radii: Optional[Sequence[int]] = None, device="cuda", _shapes=None, _dtype=None, _woffs=None):
+                 radii: Optional[Sequence[int]] = None, device="cuda", _shapes=None, _dtype=None, _woffs=None,
+                 _pitches=None):
         shapes = [tuple(im.shape) for im in images] if images is not None else list(_shapes)
         n = len(shapes)
         if n == 0:
@@ -392,14 +404,24 @@ class BatchPlan:
         self.shapes = shapes
         self.sigmas, self.scales, self.radii, self.iters_list = list(sigmas), scales, radii, [int(t) for t in iters]
         self.descs = (Desc * n)()
+        # packed images: rows padded to a multiple of 16 elements (8-bit rows
+        # start 4-byte aligned, as the matrix-core convolution needs), each
+        # image at a 256-byte aligned offset; a stack keeps its own layout
+        if _pitches is not None:
+            self.pitches = [int(x) for x in _pitches]
+        elif images is not None:
+            self.pitches = [(W + 15) // 16 * 16 for (_, W) in shapes]
+        else:
+            self.pitches = [W for (_, W) in shapes]
         wo, mo, wf, mlist, it = [], [], [], [], []
         woff = moff = foff = 0
         for i, (H, W) in enumerate(shapes):
             if images is not None and images[i].dtype != dt:
                 raise ValueError("all images of a batch share one storage dtype")
-            self.descs[i] = make_desc(H, W, sigmas[i], dt, torch.float32, scales[i], radii[i])
+            pitch = self.pitches[i]
+            self.descs[i] = make_desc(H, W, sigmas[i], dt, torch.float32, scales[i], radii[i], pitch=pitch)
             wo.append(woff if _woffs is None else int(_woffs[i]))
-            woff += H * W * esz if images is None else (H * W * esz + 255) // 256 * 256
+            woff += H * pitch * esz if images is None else (H * pitch * esz + 255) // 256 * 256
             mo.append(moff)
             moff += maps_bytes(self.descs[i])
             wf.append(foff)
@@ -420,8 +442,7 @@ class BatchPlan:
         if images is not None:
             self.weights = torch.zeros(woff // esz, dtype=dt, device=device)
             for i, img in enumerate(images):
-                H, W = img.shape
-                self.weights[wo[i] // esz: wo[i] // esz + H * W].copy_(img.reshape(-1).to(device))
+                self.image(self.weights, i).copy_(img.to(device))
         self.maps = torch.empty(self.map_bytes_total, dtype=torch.uint8, device=device)
         b = Batch(n, self.descs, self.weight_off, self.map_off, self.M, self.w_off_arr, self.iters)
         h = ctypes.c_void_p()
@@ -460,13 +481,21 @@ class BatchPlan:
             raise ValueError("the chamfer weighting starts from uint8 images")
         return BatchPlan(None, self.ms, self.sigmas, self.iters_list, [1.0 / a] * self.n, self.radii,
                          device=self.maps.device, _shapes=self.shapes, _dtype=torch.float32,
-                         _woffs=[4 * int(o) for o in self.weight_off])
+                         _woffs=[4 * int(o) for o in self.weight_off], _pitches=self.pitches)
 
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib is not None:
             _lib.itc_lattice_plan_destroy(h)
             self.handle = None
+
+    def image(self, flat: torch.Tensor, i: int) -> torch.Tensor:
+        """Image i of a flat buffer in the packed layout (the weights, a chamfer transform or labels:
+        image i starts at element weight_off[i] / stored element size): an (H, W) view at its pitch."""
+        H, W = self.shapes[i]
+        off = int(self.weight_off[i]) // torch.tensor([], dtype=self.dtype).element_size()
+        pitch = self.pitches[i]
+        return flat[off: off + H * pitch].view(H, pitch)[:, :W]
 
     def pack_codebooks(self, ws: Sequence[torch.Tensor], device="cuda") -> torch.Tensor:
         out = torch.empty((self.total_w, 2), dtype=torch.float32, device=device)

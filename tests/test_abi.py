@@ -48,15 +48,14 @@ def test_sizes_and_radius(itc):
     lib = itc.load()
     d = itc.make_desc(100, 130, 4.0)
     assert lib.itc_lattice_radius(ctypes.byref(d)) == 12
-    assert lib.itc_lattice_map_pitch(ctypes.byref(d)) == 192
-    planes = 3 * 100 * 192 * 4
-    parts = 3 * 13 * 64 * 4    # ceil(130/64) strips x ceil(100/8) groups x 64 lanes, FP32
-    sx_off = (planes + parts + 7) // 8 * 8
-    blocks = 3 * 1             # strips x ceil(13 groups / 64): FP64 block sums of the partials
-    assert itc.maps_bytes(d) == (sx_off + 8 * blocks + 255) // 256 * 256
-    # 2048 x 2048: 32 strips x 256 groups -> 32 x 4 block sums after 32 x 256 x 64 partials
+    # planes: ceil(130/16) = 9 panels of 16 columns x 100 rows
+    assert lib.itc_lattice_plane_elems(ctypes.byref(d)) == 9 * 100 * 16
+    planes = 3 * 9 * 100 * 16 * 4
+    parts = 3 * 2 * 4          # ceil(130/64) strips x ceil(100/64) row groups x 4 slots, FP64
+    assert itc.maps_bytes(d) == ((planes + 7) // 8 * 8 + 8 * parts + 255) // 256 * 256
+    # 2048 x 2048: 128 panels; 32 strips x 32 row groups x 4 partials
     dl = itc.make_desc(2048, 2048, 6.0)
-    assert itc.maps_bytes(dl) == (3 * 2048 * 2048 * 4 + 32 * 256 * 64 * 4 + 8 * 32 * 4 + 255) // 256 * 256
+    assert itc.maps_bytes(dl) == (3 * 2048 * 2048 * 4 + 8 * 32 * 32 * 4 + 255) // 256 * 256
     d2 = itc.make_desc(10, 10, 2.0, radius=5)
     assert lib.itc_lattice_radius(ctypes.byref(d2)) == 5
     d3 = itc.make_desc(10, 10, 2.5)

@@ -37,7 +37,7 @@ def test_batched_equals_per_image_bitwise(gpu_lib):
     plan, w0 = make_plan(gpu_lib, cases)
     w, sx, d, done = run_plan(plan, w0)
     for i, c in enumerate(cases):
-        img = torch.from_numpy(c.img).cuda()
+        img = plan.image(plan.weights, i)  # the packed image: same rows, same convolution kernel
         m = gpu_lib.precompute(img, c.sigma, scale=c.scale)
         wi, tr, di = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda(), c.iters)
         torch.cuda.synchronize()
@@ -74,7 +74,7 @@ def test_batched_large_codebooks(gpu_lib):
     plan, w0 = make_plan(gpu_lib, cases)
     w, sx, d, done = run_plan(plan, w0)
     for i, c in enumerate(cases):
-        m = gpu_lib.precompute(torch.from_numpy(c.img).cuda(), c.sigma, scale=c.scale)
+        m = gpu_lib.precompute(plan.image(plan.weights, i), c.sigma, scale=c.scale)
         wi, tr, _ = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda(), c.iters)
         torch.cuda.synchronize()
         assert torch.equal(plan.unpack(w, i), wi), c.name

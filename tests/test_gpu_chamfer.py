@@ -82,14 +82,10 @@ def test_chamfer_batched(gpu_lib):
     t = plan.chamfer()
     torch.cuda.synchronize()
     for i, c in enumerate(cases):
-        H, W = c.img.shape
-        off = int(plan.weight_off[i])
-        ti = t[off: off + H * W].view(H, W)
+        ti = plan.image(t, i)
         assert torch.equal(ti, gpu_lib.chamfer(torch.from_numpy(c.img).cuda())), i
     for i in (0, 17):
-        H, W = cases[i].img.shape
-        off = int(plan.weight_off[i])
-        got = t[off: off + H * W].view(H, W).cpu().numpy()
+        got = plan.image(t, i).cpu().numpy()
         assert np.array_equal(got, O.chamfer_transform(cases[i].img).astype(np.float32)), i
 
 

@@ -52,13 +52,9 @@ def test_batched_segments(gpu_lib):
     lab = plan.label(w)
     torch.cuda.synchronize()
     for i, c in enumerate(cases):
-        H, Wd = c.img.shape
-        off = int(plan.weight_off[i])
-        li = lab[off: off + H * Wd].view(H, Wd)
+        li = plan.image(lab, i)
         assert torch.equal(li, gpu_lib.label(torch.from_numpy(c.img).cuda(), plan.unpack(w, i))), i
     for i in (0, 9):
-        H, Wd = cases[i].img.shape
-        off = int(plan.weight_off[i])
-        got = lab[off: off + H * Wd].view(H, Wd).cpu().numpy()
+        got = plan.image(lab, i).cpu().numpy()
         Wi = plan.unpack(w, i).cpu().double().numpy()
         assert np.array_equal(got, O.label_pixels(cases[i].img, Wi)), i

@@ -29,8 +29,17 @@ def normwise(got, ref):
     return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
 
 
-def gpu_maps(itc, img_np, sigma, scale=1.0, radius=0, real=torch.float32):
+def gpu_maps(itc, img_np, sigma, scale=1.0, radius=0, real=torch.float32, aligned=True):
+    """Maps of a host image. 8-bit images are stored with a row pitch rounded up to 16 bytes and the
+    padding filled with 255 (the kernels must ignore it), so that they take the matrix-core
+    convolution; aligned=False keeps the contiguous layout (rows not 4-byte aligned when the width
+    is not a multiple of 4: the vector-ALU convolution)."""
     img = torch.from_numpy(np.ascontiguousarray(img_np)).to(DEV)
+    if aligned and img.dtype == torch.uint8 and img.shape[1] % 16:
+        H, W = img.shape
+        buf = torch.full((H, (W + 15) // 16 * 16), 255, dtype=torch.uint8, device=DEV)
+        buf[:, :W].copy_(img)
+        img = buf[:, :W]
     m = itc.precompute(img, sigma, scale=scale, radius=radius, real_dtype=real)
     torch.cuda.synchronize()
     return m, [p.cpu().double().numpy() for p in m.planes()], float(m.s_x.cpu()[0])
@@ -67,6 +76,26 @@ def test_maps_fp32(gpu_lib, name, build, sigma, scale, radius):
         assert normwise(g, r) <= 1e-5
     sx_ref = float(np.sum(I * ref[0]))
     assert sx == pytest.approx(sx_ref, rel=1e-6)
+
+
+UNALIGNED = [c for c in MAP_CASES if c[0] in ("ragged70x133", "gray100x77_r24", "small3x5_r6", "class_pad_r17")]
+
+
+@pytest.mark.parametrize("name,build,sigma,scale,radius", UNALIGNED, ids=[c[0] for c in UNALIGNED])
+def test_maps_unaligned_rows(gpu_lib, name, build, sigma, scale, radius):
+    """8-bit rows that do not start 4-byte aligned (contiguous images of odd width) take the
+    vector-ALU convolution; both kernels match the oracle and each other."""
+    img = build()
+    R = radius or S.radius_for(sigma)
+    _, got_v, sx_v = gpu_maps(gpu_lib, img, sigma, scale, radius, aligned=False)
+    _, got_m, sx_m = gpu_maps(gpu_lib, img, sigma, scale, radius, aligned=True)
+    I = img.astype(np.float64) * scale
+    ref = ref_maps(I, sigma, R)
+    for gv, gm, r in zip(got_v, got_m, ref):
+        assert normwise(gv, r) <= 1e-5 and normwise(gm, r) <= 1e-5
+        assert normwise(gm, gv) <= 1e-5
+    sx_ref = float(np.sum(I * ref[0]))
+    assert sx_v == pytest.approx(sx_ref, rel=1e-6) and sx_m == pytest.approx(sx_ref, rel=1e-6)
 
 
 @pytest.mark.parametrize("name,build,sigma,scale,radius", [c for c in MAP_CASES if c[2] <= 5.0],

@@ -50,11 +50,14 @@ def test_recursive_maps(gpu_lib, name, build, sigma, scale):
     for g, r in zip(got, (A, Mu, Mv)):
         assert normwise(g, r) <= 1e-6
     assert sx == pytest.approx(sx_ref, rel=1e-6)
-    # columns past the width are written as zero
-    pitch = int(m.desc.width + 63) // 64 * 64
-    if pitch > img.shape[1]:
-        raw = m.buf[: 3 * img.shape[0] * pitch * 4].view(torch.float32).view(3, img.shape[0], pitch)
-        assert torch.all(raw[:, :, img.shape[1]:] == 0)
+    # columns past the width inside the last map panel are written as zero
+    H, W = img.shape
+    full = (W + 15) // 16 * 16
+    if full > W:
+        n = gpu_lib.plane_elems(m.desc)
+        flat = m.buf[: 3 * n * 4].view(torch.float32)
+        for i in range(3):
+            assert torch.all(gpu_lib.panel_view(flat[i * n:(i + 1) * n], H, full)[:, W:] == 0)
 
 
 def test_recursive_pitch(gpu_lib):
