@@ -389,10 +389,12 @@ int32_t itc_lattice_plan_size(const itc_plan* p);
 
 /*
  * Tile shapes of a plan's convolution (the batched form of Section 3.1's
- * convolutions), for autotuning. The convolution runs one persistent launch
- * per radius class over that class's tiles: 64-column strips cut into
- * segments of about `seg_rows` rows, with `blocks_per_cu` workgroups per
- * compute unit. The maps do not depend on the shape (bitwise).
+ * convolutions), for autotuning. The tiles of a radius class are 64-column
+ * strips cut into segments of about `seg_rows` rows. Each vector-ALU class
+ * runs one persistent launch with `blocks_per_cu` workgroups per compute
+ * unit; the matrix-core classes share one persistent launch, with the
+ * smallest `blocks_per_cu` set on any of them. The maps do not depend on the
+ * shape (bitwise).
  *
  * itc_lattice_plan_conv_classes: number of classes, -1 if p is NULL.
  * itc_lattice_plan_conv_class: class c's key (stable identifier), current
@@ -400,7 +402,7 @@ int32_t itc_lattice_plan_size(const itc_plan* p);
  *   compute unit the kernel's resources allow; any output pointer may be NULL.
  *   ITC_E_NULL for a NULL plan, ITC_E_ARG for c out of range.
  * itc_lattice_plan_set_conv_shape: sets the class with key `key` to
- *   `seg_rows` (64..4096, rounded up to a multiple of 16 per image; 0 = the
+ *   `seg_rows` (64..4096, rounded up to a multiple of 64 per image; 0 = the
  *   default 256) and `blocks_per_cu` (1..the maximum; 0 = the maximum), and
  *   rebuilds and uploads its tile list (synchronous). ITC_E_ARG for an
  *   unknown key or out-of-range values. Plan set-up, not a per-call

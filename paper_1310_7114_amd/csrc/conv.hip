@@ -424,7 +424,7 @@ hipError_t launch_conv_image(bool f64, const ImageDesc& im, const void* w, void*
 
 hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, const ConvTile* d_tiles,
                              int ntiles, const void* w, void* m, int grid, hipStream_t s) {
-  if (rclass >= CONV_MX_CLASS) return launch_conv_mx_tiles(rclass - CONV_MX_CLASS, d_images, d_tiles, ntiles, w, m, grid, s);
+  if (rclass >= CONV_MX_CLASS) return hipErrorInvalidValue;  // launched by launch_conv_mx_tiles
 #define ITC_CASE_F(RR)                                                                              \
   case RR:                                                                                         \
     hipLaunchKernelGGL((conv_tiles_kernel<float, RR>), dim3(grid), dim3(CONV_NT), 0, s, d_images,    \

@@ -39,8 +39,12 @@
 //      and the taps the B operand, so the product is the transposed tile and
 //      each lane holds four adjacent columns of one output row. A 16 x 16
 //      tile of a map is then one contiguous 1 KiB of its panel, written by a
-//      single 16-byte-per-lane store; h*A is summed into an FP64 partial of
-//      S_X per SX_ROWS-row group.
+//      single 16-byte-per-lane non-temporal store; h*A is summed into an
+//      FP64 partial of S_X per SX_ROWS-row group.
+// A batch runs one persistent launch over the tiles of every radius class
+// (sorted by radius, then cost), each workgroup walking the tile sublist of
+// its XCD; a workgroup clears its shared memory when the radius of its next
+// tile differs from the last one's.
 #include <type_traits>
 
 #include "itc_device.h"
@@ -56,6 +60,9 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MX_NT = 256;  // four waves; wave w owns strip columns 16w..16w+15
 constexpr int MX_CH = 16;   // rows per chunk
+// Cache policy of the map stores: non-temporal (the maps are written once
+// and read much later, after every other image's maps have streamed past).
+constexpr int MX_STREAM = 2;
 static_assert(SX_ROWS % MX_CH == 0 && SX_SLOTS == MX_NT / 64, "one S_X slot per wave and row group");
 static_assert(CONV_TW == 4 * MAP_PANEL, "a strip is four panels");
 
@@ -319,9 +326,9 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         v4[i] = vm[i] * fac;
         sx = __builtin_fmaf((float)((hb >> (8 * i)) & 0xffu), a4[i], sx);  // zero past the width
       }
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, a4), resA, off, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, u4), resU, off, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v4), resV, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, a4), resA, off, 0, MX_STREAM);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, u4), resU, off, 0, MX_STREAM);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v4), resV, off, 0, MX_STREAM);
       sxd += ok ? (double)sx : 0.0;
       // the last chunk of an S_X row group (or of the segment): one FP64 partial per wave
       if (jo >= 0 && ((jo + 1) % (SX_ROWS / MX_CH) == 0 || jo == n_out - 1)) {  // uniform
@@ -367,16 +374,46 @@ __global__ void __launch_bounds__(MX_NT) conv_mx_image_kernel(ImageDesc im, int 
   mx_segment<RA>(im, strip, seg * S, S, wbase, mbase, smem);
 }
 
-template <int RA>
+template <int MAXRA>
+constexpr size_t mx_smem_max() {
+  size_t m = MxGeom<8>::SMEM;
+  if constexpr (MAXRA >= 16) m = m > MxGeom<16>::SMEM ? m : MxGeom<16>::SMEM;
+  if constexpr (MAXRA >= 24) m = m > MxGeom<24>::SMEM ? m : MxGeom<24>::SMEM;
+  if constexpr (MAXRA >= 32) m = m > MxGeom<32>::SMEM ? m : MxGeom<32>::SMEM;
+  return m;
+}
+
+// Persistent launch over the tiles of every aligned radius up to MAXRA:
+// workgroup b walks the sublist of its XCD, b mod CONV_XCDS.
+template <int MAXRA>
 __global__ void __launch_bounds__(MX_NT) conv_mx_tiles_kernel(const ImageDesc* __restrict__ images,
-                                                              const ConvTile* __restrict__ tiles, int ntiles,
+                                                              const ConvTile* __restrict__ tiles, XcdSplit xs,
                                                               const char* wbase, char* mbase) {
-  __shared__ __align__(16) _Float16 smem[MxGeom<RA>::SMEM / sizeof(_Float16)];
-  mx_clear_rings<RA>(smem);
-  for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+  constexpr size_t SM = mx_smem_max<MAXRA>();
+  __shared__ __align__(16) _Float16 smem[SM / sizeof(_Float16)];
+  int cur = 0;  // aligned radius whose rings the shared memory holds
+  const int x = blockIdx.x % CONV_XCDS, nx = gridDim.x / CONV_XCDS;
+  const int end = xs.beg[x + 1];
+  for (int i = xs.beg[x] + (int)blockIdx.x / CONV_XCDS; i < end; i += nx) {
     const ConvTile t = tiles[i];
     const ImageDesc im = images[t.img];
-    mx_segment<RA>(im, t.strip, t.s0, t.S, wbase, mbase, smem);
+    const int ra = (im.rclass + 7) / 8 * 8;  // uniform
+    if (ra != cur) {  // rings of another layout: clear them (warm-up reads must be finite)
+      uint32_t* p = reinterpret_cast<uint32_t*>(smem);
+      for (int k = threadIdx.x; k < (int)(SM / 4); k += MX_NT) p[k] = 0u;
+      __syncthreads();
+      cur = ra;
+    }
+    if (ra == 8) mx_segment<8>(im, t.strip, t.s0, t.S, wbase, mbase, smem);
+    if constexpr (MAXRA >= 16) {
+      if (ra == 16) mx_segment<16>(im, t.strip, t.s0, t.S, wbase, mbase, smem);
+    }
+    if constexpr (MAXRA >= 24) {
+      if (ra == 24) mx_segment<24>(im, t.strip, t.s0, t.S, wbase, mbase, smem);
+    }
+    if constexpr (MAXRA >= 32) {
+      if (ra == 32) mx_segment<32>(im, t.strip, t.s0, t.S, wbase, mbase, smem);
+    }
     __syncthreads();  // the next tile restages the shared memory
   }
 }
@@ -399,25 +436,26 @@ hipError_t launch_conv_mx_image(const ImageDesc& im, const void* w, void* m, hip
 #undef ITC_CASE
 }
 
-hipError_t launch_conv_mx_tiles(int ra, const ImageDesc* d_images, const ConvTile* d_tiles, int ntiles,
+hipError_t launch_conv_mx_tiles(int max_ra, const ImageDesc* d_images, const ConvTile* d_tiles, const XcdSplit& xs,
                                 const void* w, void* m, int grid, hipStream_t s) {
+  if (grid % CONV_XCDS != 0) return hipErrorInvalidValue;
 #define ITC_CASE(RA)                                                                                  \
   case RA:                                                                                            \
     hipLaunchKernelGGL((conv_mx_tiles_kernel<RA>), dim3(grid), dim3(MX_NT), 0, s, d_images, d_tiles,  \
-                       ntiles, (const char*)w, (char*)m);                                             \
+                       xs, (const char*)w, (char*)m);                                                 \
     return hipGetLastError();
-  switch (ra) { ITC_FOR_MX(ITC_CASE) default: return hipErrorInvalidValue; }
+  switch (max_ra) { ITC_FOR_MX(ITC_CASE) default: return hipErrorInvalidValue; }
 #undef ITC_CASE
 }
 
-int conv_mx_blocks_per_cu(int ra) {
+int conv_mx_blocks_per_cu(int max_ra) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
 #define ITC_CASE(RA)                                                                               \
   case RA:                                                                                         \
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, conv_mx_tiles_kernel<RA>, MX_NT, 0);     \
     break;
-  switch (ra) { ITC_FOR_MX(ITC_CASE) default: break; }
+  switch (max_ra) { ITC_FOR_MX(ITC_CASE) default: break; }
 #undef ITC_CASE
   return e == hipSuccess ? nb : 0;
 }

@@ -85,6 +85,17 @@ struct ConvTile {
   int32_t S;
 };
 
+// Workgroups of one launch are dealt to the chip's XCDs (each with its own
+// L2) in turn: workgroup b runs on XCD b mod CONV_XCDS. A tile list split in
+// CONV_XCDS sublists lets workgroup b take tiles from sublist b mod CONV_XCDS
+// only, so that tiles which read the same input lines (the strips of one
+// segment row, whose column halos overlap) meet in one L2. Sublist x is
+// tiles [beg[x], beg[x + 1]).
+constexpr int CONV_XCDS = 8;
+struct XcdSplit {
+  int32_t beg[CONV_XCDS + 1];
+};
+
 // Batched radius classes at or above CONV_MX_CLASS select the matrix-core
 // convolution (8-bit weights, FP32 maps) with aligned radius
 // class - CONV_MX_CLASS (a multiple of 8).
@@ -109,9 +120,12 @@ int fit_blocks_per_cu(bool f64, int m_max, int max_passes);
 // Segment rows used for a single image (multiple of CONV_CH).
 int conv_segment_rows(const ImageDesc& im);
 hipError_t launch_conv_mx_image(const ImageDesc& h_image, const void* weights, void* maps, hipStream_t s);
-hipError_t launch_conv_mx_tiles(int ra, const ImageDesc* d_images, const ConvTile* d_tiles, int ntiles,
+// One persistent launch over matrix-core tiles of aligned radii up to max_ra
+// (8, 16, 24 or 32), each workgroup walking its XCD's sublist in order
+// (grid a multiple of CONV_XCDS).
+hipError_t launch_conv_mx_tiles(int max_ra, const ImageDesc* d_images, const ConvTile* d_tiles, const XcdSplit& xs,
                                 const void* weights, void* maps, int grid, hipStream_t s);
-int conv_mx_blocks_per_cu(int ra);
+int conv_mx_blocks_per_cu(int max_ra);
 // S_X of one image: the fixed-order sum of its FP64 partials.
 hipError_t launch_sx_finalize(const ImageDesc& img, const void* maps, double* s_x, hipStream_t s);
 // 3-D lattices: one volume (slice, row, column) and its window radius.

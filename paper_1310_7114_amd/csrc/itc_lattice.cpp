@@ -139,9 +139,14 @@ struct itc_plan {
   int m_max = 0;
   int max_passes = 1;  // largest fit pass count over the images
   std::vector<ImageDesc> images;
-  // tile list grouped by radius class: [begin, end) per class
+  // convolution class keys of the plan (tile shapes are set per key) and its
+  // launches: one per vector-ALU class, one for every matrix-core class
+  // together; launch l covers tiles [launch_begin[l], launch_end[l])
   std::vector<ConvTile> tiles;
-  std::vector<int> cls, cls_begin, cls_end, cls_grid;
+  std::vector<int> cls;
+  std::vector<int> launch_key, launch_begin, launch_end, launch_grid;
+  itc::XcdSplit mx_split;  // XCD sublists of the matrix-core launch (offsets from its first tile)
+  int mx_max_ra = 0;  // largest aligned radius of the matrix-core images
   // convolution tile shape per class key (set by the autotuning hook; 0 =
   // default): target segment rows and workgroups per compute unit
   std::vector<int> key_seg, key_per;
@@ -166,8 +171,14 @@ struct itc_plan {
 // Convolution tile lists of a plan: per class key (the VALU kernel's radius
 // class, or CONV_MX_CLASS + aligned radius for the matrix-core kernel), every
 // image's strips cut into segments of about the class's target height
-// (multiples of the S_X row group), sorted by cost, most expensive first; one
-// persistent launch per class with the class's workgroups per compute unit.
+// (multiples of the S_X row group), sorted by cost, most expensive first. A
+// vector-ALU class is one persistent launch; the matrix-core classes share
+// one persistent launch, largest radius first (a workgroup then changes its
+// ring layout only a few times), with the fewest workgroups per compute unit
+// any of them asks for. Its tiles are split into one sublist per XCD: every
+// segment row of an image (the strips whose input windows overlap) goes
+// whole to the XCD with the least cost so far, so the overlapping input
+// lines are read into one L2.
 constexpr int PLAN_NKEYS = itc::CONV_MX_CLASS + 33;
 constexpr int PLAN_SEG_DEFAULT = 256, PLAN_SEG_MIN = 64, PLAN_SEG_MAX = 4096;
 
@@ -179,8 +190,9 @@ static int class_key_of(const ImageDesc& im) {
              : im.rclass;
 }
 
-static int class_occupancy(int key) {
-  const int per = itc::conv_tiles_blocks_per_cu(false, key);
+static int class_occupancy(const itc_plan* p, int key) {
+  const int per = key >= itc::CONV_MX_CLASS ? itc::conv_mx_blocks_per_cu(p->mx_max_ra)
+                                            : itc::conv_tiles_blocks_per_cu(false, key);
   return per < 1 ? 1 : per;
 }
 
@@ -205,21 +217,64 @@ static void build_conv_tiles(itc_plan* p) {
   }
   p->tiles.clear();
   p->cls.clear();
-  p->cls_begin.clear();
-  p->cls_end.clear();
-  p->cls_grid.clear();
+  p->launch_key.clear();
+  p->launch_begin.clear();
+  p->launch_end.clear();
+  p->launch_grid.clear();
   const int cus = device_cus();
-  for (int key = 0; key < PLAN_NKEYS; ++key) {
-    if (by_class[key].empty()) continue;
+  auto append_sorted = [&](int key) {
     std::vector<int> idx(by_class[key].size());
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cost_of[key][a] > cost_of[key][c]; });
-    p->cls.push_back(key);
-    p->cls_begin.push_back((int)p->tiles.size());
     for (int k : idx) p->tiles.push_back(by_class[key][k]);
-    p->cls_end.push_back((int)p->tiles.size());
-    const int per = p->key_per[key] > 0 ? p->key_per[key] : class_occupancy(key);
-    p->cls_grid.push_back(std::min(p->cls_end.back() - p->cls_begin.back(), per * cus));
+  };
+  for (int key = 0; key < PLAN_NKEYS; ++key)
+    if (!by_class[key].empty()) p->cls.push_back(key);
+  for (int key = 0; key < itc::CONV_MX_CLASS; ++key) {
+    if (by_class[key].empty()) continue;
+    p->launch_key.push_back(key);
+    p->launch_begin.push_back((int)p->tiles.size());
+    append_sorted(key);
+    p->launch_end.push_back((int)p->tiles.size());
+    const int per = p->key_per[key] > 0 ? p->key_per[key] : class_occupancy(p, key);
+    p->launch_grid.push_back(std::min(p->launch_end.back() - p->launch_begin.back(), per * cus));
+  }
+  const int begin = (int)p->tiles.size();
+  int per = class_occupancy(p, itc::CONV_MX_CLASS);
+  for (int key = PLAN_NKEYS - 1; key >= itc::CONV_MX_CLASS; --key) {
+    if (by_class[key].empty()) continue;
+    append_sorted(key);
+    if (p->key_per[key] > 0) per = std::min(per, p->key_per[key]);
+  }
+  if ((int)p->tiles.size() > begin) {
+    // deal segment rows (runs of tiles of one image and segment, adjacent
+    // after the sort) to the XCD sublists, least loaded first
+    std::vector<std::vector<ConvTile>> sub(itc::CONV_XCDS);
+    std::vector<int64_t> load(itc::CONV_XCDS, 0);
+    for (int a = begin; a < (int)p->tiles.size();) {
+      int b = a;
+      int64_t cost = 0;
+      while (b < (int)p->tiles.size() && p->tiles[b].img == p->tiles[a].img && p->tiles[b].s0 == p->tiles[a].s0) {
+        const ImageDesc& im = p->images[p->tiles[b].img];
+        cost += std::min(p->tiles[b].S, im.H - p->tiles[b].s0) + 2 * itc::conv_mx_radius(im.rclass);
+        ++b;
+      }
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      sub[x].insert(sub[x].end(), p->tiles.begin() + a, p->tiles.begin() + b);
+      load[x] += cost;
+      a = b;
+    }
+    p->tiles.resize(begin);
+    for (int x = 0; x < itc::CONV_XCDS; ++x) {
+      p->mx_split.beg[x] = (int)p->tiles.size() - begin;
+      p->tiles.insert(p->tiles.end(), sub[x].begin(), sub[x].end());
+    }
+    p->mx_split.beg[itc::CONV_XCDS] = (int)p->tiles.size() - begin;
+    const int grid = std::max(itc::CONV_XCDS, per * cus / itc::CONV_XCDS * itc::CONV_XCDS);
+    p->launch_key.push_back(itc::CONV_MX_CLASS + p->mx_max_ra);
+    p->launch_begin.push_back(begin);
+    p->launch_end.push_back((int)p->tiles.size());
+    p->launch_grid.push_back(grid);
   }
 }
 
@@ -425,6 +480,8 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   }
   p->key_seg.assign(PLAN_NKEYS, 0);
   p->key_per.assign(PLAN_NKEYS, 0);
+  for (const ImageDesc& im : p->images)
+    if (class_key_of(im) >= itc::CONV_MX_CLASS) p->mx_max_ra = std::max(p->mx_max_ra, itc::conv_mx_radius(im.rclass));
   build_conv_tiles(p);
   p->order.resize(b->n);
   std::iota(p->order.begin(), p->order.end(), 0);
@@ -489,8 +546,8 @@ itc_status itc_lattice_plan_conv_class(const itc_plan* p, int32_t c, int32_t* ke
   const int k = p->cls[c];
   if (key) *key = k;
   if (seg_rows) *seg_rows = p->key_seg[k] > 0 ? p->key_seg[k] : PLAN_SEG_DEFAULT;
-  if (blocks_per_cu) *blocks_per_cu = p->key_per[k] > 0 ? p->key_per[k] : class_occupancy(k);
-  if (max_blocks_per_cu) *max_blocks_per_cu = class_occupancy(k);
+  if (blocks_per_cu) *blocks_per_cu = p->key_per[k] > 0 ? p->key_per[k] : class_occupancy(p, k);
+  if (max_blocks_per_cu) *max_blocks_per_cu = class_occupancy(p, k);
   return ok();
 }
 
@@ -500,8 +557,9 @@ itc_status itc_lattice_plan_set_conv_shape(itc_plan* p, int32_t key, int32_t seg
     return fail(ITC_E_ARG, "class key %d is not a convolution class of this plan", key);
   if (seg_rows != 0 && (seg_rows < PLAN_SEG_MIN || seg_rows > PLAN_SEG_MAX))
     return fail(ITC_E_ARG, "segment rows %d outside [%d, %d]", seg_rows, PLAN_SEG_MIN, PLAN_SEG_MAX);
-  if (blocks_per_cu < 0 || blocks_per_cu > class_occupancy(key))
-    return fail(ITC_E_ARG, "workgroups per compute unit %d outside [0, %d]", blocks_per_cu, class_occupancy(key));
+  if (blocks_per_cu < 0 || blocks_per_cu > class_occupancy(p, key))
+    return fail(ITC_E_ARG, "workgroups per compute unit %d outside [0, %d]", blocks_per_cu,
+                class_occupancy(p, key));
   p->key_seg[key] = seg_rows;
   p->key_per[key] = blocks_per_cu;
   build_conv_tiles(p);
@@ -565,10 +623,15 @@ itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void
   if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
   if (p->any_mx && (uintptr_t)weights % 4 != 0)
     return fail(ITC_E_ARG, "8-bit weights must be 4-byte aligned (the images' offsets and pitches are)");
-  for (size_t c = 0; c < p->cls.size(); ++c) {
-    hipError_t e = itc::launch_conv_tiles(false, p->cls[c], p->d_images, p->d_tiles + p->cls_begin[c],
-                                          p->cls_end[c] - p->cls_begin[c], weights, maps, p->cls_grid[c],
-                                          (hipStream_t)stream);
+  for (size_t l = 0; l < p->launch_key.size(); ++l) {
+    const int key = p->launch_key[l];
+    hipError_t e =
+        key >= itc::CONV_MX_CLASS
+            ? itc::launch_conv_mx_tiles(key - itc::CONV_MX_CLASS, p->d_images, p->d_tiles + p->launch_begin[l],
+                                        p->mx_split, weights, maps, p->launch_grid[l], (hipStream_t)stream)
+            : itc::launch_conv_tiles(false, key, p->d_images, p->d_tiles + p->launch_begin[l],
+                                     p->launch_end[l] - p->launch_begin[l], weights, maps, p->launch_grid[l],
+                                     (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "batched convolution launch");
   }
   return ok();
