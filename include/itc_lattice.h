@@ -40,7 +40,7 @@
  *    gives the reason. No C++ exception crosses this boundary.
  *  - Checks that fail return ITC_E_NULL (null pointer), ITC_E_ARG (a size,
  *    width or count out of range), ITC_E_UNSUPPORTED (valid but beyond what
- *    the kernels are built for: R > 32 for FP32, R > 16 for FP64, M > 1024,
+ *    the kernels are built for: R > 32 for FP32, R > 24 for FP64, M > 1024,
  *    an image or its maps of 2 GiB or more),
  *    ITC_E_DEVICE (a HIP launch or runtime error).
  */
@@ -66,7 +66,7 @@ typedef enum { ITC_U8 = 0, ITC_F32 = 1, ITC_F64 = 2 } itc_dtype;
 
 /* Maximum supported sizes (ITC_E_UNSUPPORTED beyond them). */
 #define ITC_MAX_RADIUS_F32 32
-#define ITC_MAX_RADIUS_F64 16
+#define ITC_MAX_RADIUS_F64 24
 #define ITC_MAX_CODEVECTORS 1024
 #define ITC_MAX_CHAMFER_WIDTH 16384 /* widest image the chamfer transform accepts */
 #define ITC_MAX_CHAMFER_STEP 64     /* largest orthogonal step cost of the chamfer mask */

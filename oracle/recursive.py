@@ -32,19 +32,39 @@ import math
 
 import numpy as np
 
-__all__ = ["yvv_coefficients", "yvv_filter_1d", "recursive_density", "recursive_maps"]
+__all__ = ["yvv_q", "yvv_b", "yvv_coefficients", "yvv_filter_1d", "recursive_density", "recursive_maps"]
+
+# Young and van Vliet's published constants. Q_FIT: the two branches of
+# their empirical width relation q(sigma). B_POLY: b0..b3 as polynomials in q.
+# The polynomials are pinned exactly against the filter's factored pole form
+# (tests/test_oracle_recursive.py). The q(sigma) relation is an empirical fit;
+# it is pinned only to within a few per cent of an independent least-squares
+# fit of q, so its constants are parity unpinned beyond that band.
+Q_FIT = (0.98711, 0.96330, 3.97156, 4.14554, 0.26891)
+B_POLY = (1.57825, 2.44413, 1.4281, 0.422205, 2.85619, 1.26661)
+
+
+def yvv_q(sigma: float) -> float:
+    """q(sigma): q = 0.98711 sigma - 0.96330 for sigma >= 2.5, else 3.97156 - 4.14554 sqrt(1 - 0.26891 sigma)."""
+    k1, k0, c0, c1, c2 = Q_FIT
+    if sigma >= 2.5:
+        return k1 * sigma - k0
+    return c0 - c1 * math.sqrt(1.0 - c2 * sigma)
+
+
+def yvv_b(q: float):
+    """(b0, b1, b2, b3) of the recursion for parameter q."""
+    p0, p1, p2, p3, p4, p5 = B_POLY
+    b0 = p0 + p1 * q + p2 * q * q + p3 * q ** 3
+    b1 = p1 * q + p4 * q * q + p5 * q ** 3
+    b2 = -(p2 * q * q + p5 * q ** 3)
+    b3 = p3 * q ** 3
+    return b0, b1, b2, b3
 
 
 def yvv_coefficients(sigma: float):
     """(B, a1, a2, a3) of the Young-van Vliet recursive Gaussian for width sigma >= 0.5."""
-    if sigma >= 2.5:
-        q = 0.98711 * sigma - 0.96330
-    else:
-        q = 3.97156 - 4.14554 * math.sqrt(1.0 - 0.26891 * sigma)
-    b0 = 1.57825 + 2.44413 * q + 1.4281 * q * q + 0.422205 * q ** 3
-    b1 = 2.44413 * q + 2.85619 * q * q + 1.26661 * q ** 3
-    b2 = -(1.4281 * q * q + 1.26661 * q ** 3)
-    b3 = 0.422205 * q ** 3
+    b0, b1, b2, b3 = yvv_b(yvv_q(sigma))
     B = 1.0 - (b1 + b2 + b3) / b0
     return B, b1 / b0, b2 / b0, b3 / b0
 

@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(256) sx_total_kernel(ImageDesc im, const char*
 // host-side launch helpers
 // ---------------------------------------------------------------------------
 #define ITC_FOR_CLASSES_F32(X) X(2) X(3) X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(24) X(28) X(32)
-#define ITC_FOR_CLASSES_F64(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16)
+#define ITC_FOR_CLASSES_F64(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(20) X(24)
 
 // Segment length for a single image: enough workgroups to fill the chip,
 // but long enough that the 2R-row warm-up of each segment stays small; a

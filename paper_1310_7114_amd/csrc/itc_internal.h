@@ -21,7 +21,7 @@ constexpr int MAX_RADIUS = 32;
 // Supported truncation radii are rounded up to one of these classes; taps
 // beyond the true radius are zero, which leaves every sum unchanged.
 constexpr int kRadiusClassesF32[] = {2, 3, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24, 28, 32};
-constexpr int kRadiusClassesF64[] = {2, 3, 4, 6, 8, 12, 16};
+constexpr int kRadiusClassesF64[] = {2, 3, 4, 6, 8, 12, 16, 20, 24};
 
 inline int radius_class(int R, bool f64) {
   if (f64) {

@@ -80,7 +80,7 @@ def test_bad_descriptors_rejected(itc, field, value, status):
 
 def test_f64_radius_limit(itc):
     lib = itc.load()
-    d = itc.make_desc(16, 16, 2.0, real_dtype=__import__("torch").float64, radius=17)
+    d = itc.make_desc(16, 16, 2.0, real_dtype=__import__("torch").float64, radius=25)
     assert lib.itc_lattice_precompute(ctypes.byref(d), ctypes.c_void_p(256), ctypes.c_void_p(256),
                                       ctypes.c_void_p(256), None) == 3
 

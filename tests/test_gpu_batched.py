@@ -131,6 +131,97 @@ def test_full_batch_divergence_every_image(gpu_lib):
     assert err.max() <= 1e-5, (int(err.argmax()), float(err.max()))
 
 
+# ---------------------------------------------------------------------------
+# every codebook of the silhouette batch against the oracle
+# ---------------------------------------------------------------------------
+_CASES = None  # the batch, shared with forked oracle workers
+
+
+def _oracle_final(i):
+    c = _CASES[i]
+    W, tr, _, _ = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters)
+    return W, float(tr[-1])
+
+
+def _oracle_exception(args):
+    """Oracle evidence at a codebook W_gpu that is farther than 1e-3 px from the oracle's:
+    D at W_gpu, the length of one oracle sweep from W_gpu, the oracle's own last sweep length,
+    and the spread FP64 rounding alone gives the oracle's final codebook (maps times 1 + 1e-15 xi)."""
+    i, wg, W100 = args
+    c = _CASES[i]
+    maps = O.lattice_maps(c.weights, c.sigma, c.R)
+    d_at = O.lattice_divergence(c.weights, maps, wg, c.sigma)
+    w1 = O.fit_lattice(c.weights, wg, c.sigma, c.R, 1, maps=maps)[0]
+    W99 = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters - 1, maps=maps)[0]
+    rng = np.random.default_rng(i)
+    noisy = tuple(m * (1.0 + 1e-15 * rng.standard_normal(m.shape)) for m in maps)
+    Wn = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters, maps=noisy)[0]
+    step = lambda a, b: float(np.linalg.norm(a - b, axis=1).max())  # noqa: E731
+    return d_at, step(w1, wg), step(W100, W99), step(Wn, W100)
+
+
+def test_full_batch_codebooks_every_image(gpu_lib):
+    """All 1,400 silhouettes in the benchmark's launch: every final codebook is within 1e-3 px of the
+    oracle's, except on ill-conditioned images, where it must be a state the oracle's own iteration
+    accepts. On those images (about 18, sigma 4 and 8, still moving 0.02-0.2 px per sweep after the
+    100 sweeps) rounding the oracle's own maps to FP32 alone moves its codebook by 1e-3 to 54 px, so no
+    FP32 computation meets the 1e-3 px bar there. For each exception:
+      - the oracle's D at the GPU codebook is within 1e-5 max(1, |D|) of the oracle's final D;
+      - one oracle sweep from the GPU codebook moves it no farther than 1.05 times the oracle's own
+        last sweep, plus 1e-4 px (the GPU codebook is at the same stage of the iteration);
+      - the FP64 instantiation of the kernels (FP64 maps and fit, same image) is within
+        max(1e-9, 20 s) px of the oracle, s the spread that FP64 rounding alone gives the oracle
+        (its maps times 1 + 1e-15 N(0, 1)), which proves the kernels on those images."""
+    import multiprocessing as mp
+
+    global _CASES
+    cases = S.config3_cases()
+    _CASES = cases
+    plan, w0 = make_plan(gpu_lib, cases)
+    w, sx, d, done = run_plan(plan, w0)
+    assert torch.all(done == 100)
+    wg_all = w.cpu().double().numpy()
+    nproc = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(nproc) as pool:
+        ref = pool.map(_oracle_final, range(len(cases)), chunksize=4)
+        exc = []
+        for i, c in enumerate(cases):
+            wg = wg_all[plan.w_offsets[i]: plan.w_offsets[i] + c.M]
+            if np.linalg.norm(wg - ref[i][0], axis=1).max() > 1e-3:
+                exc.append((i, wg, ref[i][0]))
+        evidence = pool.map(_oracle_exception, exc)
+    print(f"{len(exc)} of {len(cases)} codebooks beyond 1e-3 px: {[e[0] for e in exc]}")
+    assert len(exc) <= 40
+    for (i, wg, W100), (d_at, step_gpu, step_last, spread) in zip(exc, evidence):
+        c = cases[i]
+        D = ref[i][1]
+        assert c.sigma >= 4.0, i
+        assert abs(d_at - D) <= 1e-5 * max(1.0, abs(D)), (i, d_at, D)
+        assert step_gpu <= 1.05 * step_last + 1e-4, (i, step_gpu, step_last)
+        m = gpu_lib.precompute(plan.image(plan.weights, i), c.sigma, scale=c.scale, real_dtype=torch.float64)
+        w64, _, _ = gpu_lib.fit(m, torch.from_numpy(c.w0).cuda().double(), c.iters)
+        torch.cuda.synchronize()
+        err64 = float(np.linalg.norm(w64.cpu().numpy() - W100, axis=1).max())
+        assert err64 <= max(1e-9, 20.0 * spread), (i, err64, spread)
+
+
+def test_full_batch_maps_largest_per_sigma(gpu_lib):
+    """The maps of the largest silhouette of each sigma class, as the batched launch wrote them, against
+    the oracle element by element (normwise 1e-5 per plane) and S_X (1e-6)."""
+    cases = S.config3_cases()
+    plan, w0 = make_plan(gpu_lib, cases)
+    w, sx, d, done = run_plan(plan, w0)
+    for sigma in (2.0, 4.0, 8.0):
+        i = max((k for k, c in enumerate(cases) if c.sigma == sigma), key=lambda k: cases[k].img.size)
+        c = cases[i]
+        got = [p.cpu().double().numpy() for p in plan.maps_of(i).planes()]
+        A, Bu, Bv = O.lattice_maps(c.weights, c.sigma, c.R)
+        ref = (A,) + tuple(O.moment_maps(A, Bu, Bv))
+        for g, r in zip(got, ref):
+            assert float(np.abs(g - r).max() / np.abs(r).max()) <= 1e-5, (i, sigma)
+        assert float(sx[i]) == pytest.approx(float(np.sum(c.weights * A)), rel=1e-6)
+
+
 def test_batched_theta_and_graph_replay(gpu_lib):
     """The plan's launches capture into a HIP graph; every replay matches eager."""
     cases = S.config3_cases(indices=range(100, 116))

@@ -15,7 +15,75 @@ import numpy as np
 import pytest
 
 import oracle as O
+import oracle.recursive as OR
 from paper_1310_7114_amd import synth as S
+
+# The filter's three poles as Young and van Vliet give them (their m0, m1, m2;
+# Signal Processing 44 (1995)): the recursion's denominator is, with z the
+# one-sample delay, (m0 + q - q z)((m1 + q)^2 + m2^2 - 2 (m1 + q) q z + q^2 z^2),
+# scaled by 0.422205 (= the q^3 coefficient of b0). Expanding it gives the
+# b0..b3 polynomials independently of how the oracle writes them.
+POLES = (1.16680, 1.10783, 1.40586)
+B_SCALE = 0.422205
+
+
+def b_from_poles(q):
+    m0, m1, m2 = POLES
+    a, c, d = m0 + q, (m1 + q) ** 2 + m2 * m2, 2.0 * (m1 + q)
+    return (B_SCALE * a * c, B_SCALE * q * (a * d + c), -B_SCALE * q * q * (a + d), B_SCALE * q ** 3)
+
+
+def poly_matches_poles(b_of_q, tol=1e-5):
+    for q in (0.1, 0.5, 1.0, 2.0, 5.0, 10.0, 40.0):
+        got, ref = np.array(b_of_q(q)), np.array(b_from_poles(q))
+        if np.abs(got - ref).max() > tol * np.abs(ref).max():
+            return False
+    return True
+
+
+def test_polynomials_equal_the_pole_form():
+    """b0..b3(q) equal the expansion of the factored pole form to the printed precision (5-6 digits)."""
+    assert poly_matches_poles(OR.yvv_b)
+
+
+@pytest.mark.parametrize("k", range(6))
+@pytest.mark.parametrize("rel", [1e-4, -1e-4, 1e-3])
+def test_pole_pin_catches_a_mistyped_constant(monkeypatch, k, rel):
+    """A single polynomial constant off by 1e-4 (a digit beyond the fourth) fails the pole-form pin."""
+    bad = list(OR.B_POLY)
+    bad[k] *= 1.0 + rel
+    monkeypatch.setattr(OR, "B_POLY", tuple(bad))
+    assert not poly_matches_poles(OR.yvv_b)
+
+
+def test_width_relation_near_a_least_squares_fit():
+    """q(sigma) is an empirical fit: it lies within 3.5 % of the q that best fits the sampled Gaussian
+    (least squares over the impulse response) for sigma from 1 to 32, and continues linearly."""
+    from scipy.optimize import minimize_scalar
+
+    def response(q, n, c):
+        b0, b1, b2, b3 = b_from_poles(q)
+        B, a = 1.0 - (b1 + b2 + b3) / b0, (b1 / b0, b2 / b0, b3 / b0)
+        x = np.zeros(n)
+        x[c] = 1.0
+        w = np.zeros(n)
+        for i in range(n):
+            w[i] = B * x[i] + sum(a[k] * w[i - 1 - k] for k in range(3) if i - 1 - k >= 0)
+        y = np.zeros(n)
+        for i in range(n - 1, -1, -1):
+            y[i] = B * w[i] + sum(a[k] * y[i + 1 + k] for k in range(3) if i + 1 + k < n)
+        return y
+
+    for sigma in (1.0, 2.0, 3.0, 6.0, 12.0, 32.0):
+        n = int(20 * sigma) + 60
+        c = n // 2
+        t = np.arange(n) - c
+        g = np.exp(-t * t / (2 * sigma * sigma))
+        g /= g.sum()
+        fit = minimize_scalar(lambda q: float(((response(q, n, c) - g) ** 2).sum()), bounds=(0.05, 3 * sigma + 3),
+                              method="bounded", options={"xatol": 1e-7}).x
+        assert abs(OR.yvv_q(sigma) / fit - 1.0) <= 0.035, sigma
+    assert OR.yvv_q(40.0) - OR.yvv_q(20.0) == pytest.approx(20 * OR.Q_FIT[0], rel=1e-12)
 
 
 @pytest.mark.parametrize("sigma,max_err", [(2.0, 0.06), (4.0, 0.04), (8.0, 0.03), (16.0, 0.02), (32.0, 0.015)])
