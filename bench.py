@@ -23,13 +23,16 @@ if ROOT not in sys.path:
 
 METRIC = "images/sec to converged codebook (batched vs per-image); conv HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
-# MI355X vector FP32 peak (256 CUs, 2.4 GHz). The kernels are compiled without
-# packed FP32 instructions, but the chip's unpacked FP32 FMA throughput measures above half
-# of this figure, so half of it would not bound the kernel.
-VALU_PEAK_TFLOPS = 157.3
-# one ordered codebook pair of a sweep: 2 differences, |d|^2 (mul + fma), exp2,
-# C += e, Cu += e du, Cv += e dv
-FIT_FLOPS_PER_PAIR = 11.0
+# Convolution: algorithmic bytes per pixel, 1 B of 8-bit weight in and 3 x 4 B of FP32 maps out.
+CONV_BYTES_PER_PX = 13.0
+# Fit: algorithmic work per unordered codebook pair of a sweep (the M(M-1)/2 distinct pairs):
+# 2 differences, |d|^2 (mul + fma), one exp2, C_k and C_j (2 adds), E_k and E_j (4 fmas) = 16 flop
+# in 10 FP32 VALU instructions and one transcendental. Its ceiling comes from the issue rates a probe
+# kernel measures on the chip, in SIMD cycles per wave64 instruction: unpacked FP32 3.1 (the build
+# disables packed FP32), v_exp_f32 9.8; 256 CUs x 4 SIMDs at 2.4 GHz.
+FIT_FLOPS_PER_PAIR = 16.0
+FIT_VALU_PER_PAIR, FIT_VALU_CYCLES, FIT_EXP_CYCLES = 10, 3.1, 9.8
+FIT_PEAK_PAIRS_PER_S = 1024 * 2.4e9 * 64.0 / (FIT_VALU_PER_PAIR * FIT_VALU_CYCLES + FIT_EXP_CYCLES)
 
 
 def profile_figures(group: str):
@@ -54,6 +57,12 @@ def profile_figures(group: str):
         return {k: float(kv[k]) for k in ("traffic_bytes_per_step", "average_us_per_step")}
     except (KeyError, OSError, ValueError):
         return None
+
+
+def paper_widths(N: float, M: int):
+    """(xi, omega) of the paper's runtime experiments (Section 4): omega = sqrt(N/M)/2, xi = omega/2."""
+    omega = (float(N) / M) ** 0.5 / 2.0
+    return omega / 2.0, omega
 
 
 def _pool_init():
@@ -182,7 +191,9 @@ def cpu_legs(cases, seconds):
 def gpu_extras(dev, cases, itc, synth):
     """Secondary measurements: device copy and fill rates, the convolution per
     sigma class of the silhouette batch, the single-image workloads (512^2 and
-    2048^2) end to end, and the convolution of the 64-image 1024^2 batch."""
+    2048^2) end to end, differentiation of the 64-image 1024^2 batch, the
+    theta stop, and the convolution of the 64-image 1024^2 batch."""
+    import numpy as np
     import torch
 
     def timed(fn, reps=5):
@@ -293,7 +304,7 @@ def gpu_extras(dev, cases, itc, synth):
     # Algorithm 1 as printed (eq. (6), lattice codevectors) on the 512 x 512
     # shapes with the paper's widths: time per sweep (the paper's Fig. 4 metric)
     c2 = synth.config2_case(0)
-    xi2, om2 = itc.paper_widths(float(c2.img.sum()), c2.M)
+    xi2, om2 = paper_widths(float(c2.img.sum()), c2.M)
     x2 = torch.from_numpy(c2.img).to(dev)
     w02 = torch.from_numpy(c2.w0).to(dev).to(torch.int32)
     work = torch.empty(1 << 26, dtype=torch.uint8, device=dev)
@@ -339,7 +350,54 @@ def gpu_extras(dev, cases, itc, synth):
                                 "volumes_per_s": 1.0 / (t_vm + t_vf)}
     del vm
 
+    # differentiation: forward D and the adjoint (dD/dw, dD/dh) of 64 weighted
+    # 1024 x 1024 images, M = 256, sigma = 4, FP32 per-pixel weights h = g/255
+    # (the autograd path: FP32 weights take the vector-ALU convolution)
     c5 = synth.config5_cases(64)
+    B5, H5, W5, M5 = len(c5), 1024, 1024, 256
+    p5 = itc.BatchPlan.for_stack(B5, H5, W5, M5, 4.0, iters=0, dtype=torch.float32, device=dev)
+    h5 = torch.stack([torch.from_numpy(c.img) for c in c5]).to(dev).float() / 255.0
+    w5 = torch.cat([torch.from_numpy(c.w0) for c in c5]).to(dev, torch.float32)
+    maps5 = p5.new_maps()
+    wout5 = torch.empty_like(w5)
+    sx5 = torch.empty(B5, dtype=torch.float64, device=dev)
+    d5 = torch.empty(B5, dtype=torch.float64, device=dev)
+    gd5 = torch.ones(B5, dtype=torch.float64, device=dev)
+    gw5 = torch.empty_like(w5)
+    gh5 = torch.empty((B5, H5, W5), dtype=torch.float32, device=dev)
+    f_conv = lambda: p5.precompute(weights=h5, maps=maps5)  # noqa: E731
+    f_d = lambda: p5.fit(w5, wout5, s_x=sx5, d_out=d5, maps=maps5)  # noqa: E731
+    f_gw = lambda: p5.backward(w5, sx5, gd5, grad_w=gw5, maps=maps5)  # noqa: E731
+    f_gh = lambda: p5.backward(w5, sx5, gd5, grad_weights=gh5, maps=maps5)  # noqa: E731
+    parts = {k: timed(f) for k, f in (("conv", f_conv), ("divergence", f_d), ("grad_w", f_gw), ("grad_h", f_gh))}
+    tot = sum(parts.values())
+    px5 = float(B5 * H5 * W5)
+    out["differentiation_gray1024x64"] = {
+        "images": B5, "M": M5, "sigma": 4.0, "weights": "FP32", "images_per_s": B5 / tot, "ms_total": tot * 1e3,
+        "ms": {k: v * 1e3 for k, v in parts.items()},
+        "conv_gbs_algorithmic": 16.0 * px5 / parts["conv"] / 1e9, "conv_bytes_per_px": 16,
+        "grad_h_gbs_algorithmic": 8.0 * px5 / parts["grad_h"] / 1e9, "grad_h_bytes_per_px": 8}
+    del p5, maps5, gh5, h5
+
+    # convergence: the theta stop on the silhouettes (largest codevector step <= theta px)
+    pc = itc.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases], [c.sigma for c in cases],
+                       [c.iters for c in cases], device=dev)
+    w0c = pc.pack_codebooks([c.w0 for c in cases], device=dev)
+    wc = torch.empty_like(w0c)
+    sxc = torch.empty(len(cases), dtype=torch.float64, device=dev)
+    dc = torch.empty_like(sxc)
+    donec = torch.empty(len(cases), dtype=torch.int32, device=dev)
+    conv_t = []
+    for theta in (1e-2, 1e-3):
+        t_run = timed(lambda: pc.run(w0c, wc, sxc, dc, donec, theta=theta), reps=3)
+        k = donec.cpu().numpy()
+        conv_t.append({"theta_px": theta, "images_per_s": len(cases) / t_run, "ms": t_run * 1e3,
+                       "sweeps_median": float(np.median(k)), "sweeps_p90": float(np.percentile(k, 90)),
+                       "sweeps_max": int(k.max()), "fraction_under_20": float(np.mean(k < 20)),
+                       "fraction_stopped": float(np.mean(k < 100))})
+    out["theta_stop_silhouettes"] = conv_t
+    del pc
+
     p = itc.BatchPlan([torch.from_numpy(c.img) for c in c5], [c.M for c in c5], [c.sigma for c in c5],
                       [c.iters for c in c5], device=dev)
     t = timed(p.precompute)
@@ -353,8 +411,8 @@ def gpu_extras(dev, cases, itc, synth):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--images", type=int, default=1400, help="silhouettes in the batch")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle leg")
     p.add_argument("--no-cpu", action="store_true")
@@ -422,47 +480,51 @@ def main():
     dd = torch.empty(n, dtype=torch.float64, device=dev)
     done = torch.empty(n, dtype=torch.int32, device=dev)
 
-    # ---------------- batched step captured in a HIP graph ----------------
-    s = torch.cuda.Stream(device=dev)
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        for _ in range(max(1, args.warmup)):
-            plan.run(w0, w, sx, dd, done)
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
+    # ---------------- batched step: two HIP graphs (convolution, fit + D) ----------------
+    # The convolution of an 8-bit batch is one persistent kernel launch and the
+    # fit another; each is captured in a graph of its own, and HIP events
+    # recorded between the replays (on the replay stream) time every launch of
+    # the timed steps.
+    def capture(fn):
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    conv_fn = plan.precompute
+    fit_fn = lambda: plan.fit(w0, w, sx, dd, done)  # noqa: E731
     if args.eager:
-        step = lambda: plan.run(w0, w, sx, dd, done)  # noqa: E731
+        conv_step, fit_step = conv_fn, fit_fn
     else:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            plan.run(w0, w, sx, dd, done)
-        step = graph.replay
-    for _ in range(args.warmup):
-        step()
+        g_conv, g_fit = capture(conv_fn), capture(fit_fn)
+        conv_step, fit_step = g_conv.replay, g_fit.replay
+    for _ in range(max(1, args.warmup)):
+        conv_step()
+        fit_step()
     torch.cuda.synchronize()
     print("[bench] warm-up done; timing batched steps", file=sys.stderr, flush=True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        evs[k][0].record()
+        conv_step()
+        evs[k][1].record()
+        fit_step()
+        evs[k][2].record()
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t) / args.steps
     assert bool(torch.all(done == 100)) and bool(torch.all(torch.isfinite(dd)))
-
-    # ---------------- per-phase timing with events on the launch stream ----------------
-    cur = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    conv_ms, fit_ms = [], []
-    for _ in range(args.steps):
-        ev[0].record(cur)
-        plan.precompute()
-        ev[1].record(cur)
-        plan.fit(w0, w, sx, dd, done)
-        ev[2].record(cur)
-        torch.cuda.synchronize()
-        conv_ms.append(ev[0].elapsed_time(ev[1]))
-        fit_ms.append(ev[1].elapsed_time(ev[2]))
-    conv_s = float(np.mean(conv_ms)) / 1e3
-    fit_s = float(np.mean(fit_ms)) / 1e3
+    conv_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    fit_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    conv_s = float(np.median(conv_ms)) / 1e3
+    fit_s = float(np.median(fit_ms)) / 1e3
+    conv_launches = plan.conv_launches()
 
     # ---------------- secondary: the step with its weights uploaded from pinned host memory ----------------
     # (the library takes device buffers; this is the rate with the PCIe upload included, never `value`)
@@ -479,7 +541,8 @@ def main():
         t = time.perf_counter()
         for _ in range(args.steps):
             plan.weights.copy_(host_w, non_blocking=True)
-            step()
+            conv_step()
+            fit_step()
         torch.cuda.synchronize()
         both_s = (time.perf_counter() - t) / args.steps
         nbytes = host_w.numel() * host_w.element_size()
@@ -487,16 +550,18 @@ def main():
                 "note": "pinned host-to-device upload of the packed 8-bit weights before every step"}
         del host_w
 
-    # algorithmic work of the convolution: 1 B in + 3 x 4 B out per pixel;
-    # 5 filters x (2R+1) taps FMA per pixel (2 flop each) in the direct form
-    conv_bytes = 13.0 * npx
+    # algorithmic work of the convolution (13 B per pixel) over the median
+    # duration of its launch; 5 filters x (2R+1) taps FMA per pixel (2 flop
+    # each) is what the direct form would compute
+    conv_bytes = CONV_BYTES_PER_PX * npx
     conv_flops = float(sum(2.0 * 5 * (2 * c.R + 1) * c.img.size for c in cases))
     conv_gbs = conv_bytes / conv_s / 1e9
     conv_tfs = conv_flops / conv_s / 1e12
-    # algorithmic work of the fit (the dominant single kernel): every sweep,
-    # and the final divergence, evaluates all M^2 ordered codebook pairs
-    fit_flops = FIT_FLOPS_PER_PAIR * float(sum((c.iters + 1) * c.M * c.M for c in cases))
-    fit_tfs = fit_flops / fit_s / 1e12
+    # algorithmic work of the fit: every sweep, and the final divergence,
+    # evaluates the M(M-1)/2 distinct codebook pairs of every image
+    fit_pairs = float(sum((c.iters + 1) * c.M * (c.M - 1) / 2 for c in cases))
+    fit_tfs = FIT_FLOPS_PER_PAIR * fit_pairs / fit_s / 1e12
+    fit_peak_tfs = FIT_FLOPS_PER_PAIR * FIT_PEAK_PAIRS_PER_S / 1e12
     fit_prof = profile_figures("fit_silhouettes1400")
     conv_prof = profile_figures("conv_silhouettes1400")
 
@@ -520,12 +585,7 @@ def main():
                                          itc._stream())
                 itc._check(st)
 
-        with torch.cuda.stream(s):
-            loop()
-        torch.cuda.synchronize()
-        pg = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(pg):
-            loop()
+        pg = capture(loop)
         pg.replay()
         torch.cuda.synchronize()
         reps = max(1, min(3, args.steps))
@@ -561,21 +621,24 @@ def main():
                                f"M 10..200, sigma 2/4/8, 100 sweeps, batched persistent + "
                                + ("stream launches" if args.eager else "HIP graph"),
                    "images": n, "pixels": npx, "iters": 100},
-        "phases_ms": {"conv": conv_s * 1e3, "fit_and_divergence": fit_s * 1e3},
+        "phases_ms": {"conv": conv_s * 1e3, "fit_and_divergence": fit_s * 1e3,
+                      "timing": f"median over the {args.steps} timed steps, HIP events between graph replays"},
         "per_image": per_image,
         "pcie_inclusive": pcie,
         "autotune": tuned,
         "batched_over_per_image": (value / per_image["value"]) if per_image else None,
-        "roofline": {"bound": "alu", "achieved": fit_tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": fit_tfs / VALU_PEAK_TFLOPS,
-                     "traffic": fit_prof["traffic_bytes_per_step"] if fit_prof else None,
-                     "kernel": "fit_batched_kernel (all sweeps + D, one launch)",
-                     "flops_per_pair": FIT_FLOPS_PER_PAIR},
-        "conv_hbm": {"bound": "hbm", "achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": conv_gbs / HBM_PEAK_GBS, "bytes_per_px": 13,
+        "roofline": {"bound": "hbm", "achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": conv_gbs / HBM_PEAK_GBS,
                      "traffic": conv_prof["traffic_bytes_per_step"] if conv_prof else None,
-                     "direct_form_tflops": conv_tfs,
-                     "kernel": "conv_mx_tiles_kernel (one launch per aligned radius)"},
+                     "kernel": "conv_mx_tiles_kernel (one persistent launch per step)",
+                     "launches_per_step": conv_launches, "bytes_per_px": CONV_BYTES_PER_PX,
+                     "algorithmic_bytes": conv_bytes, "ms": conv_s * 1e3,
+                     "direct_form_tflops": conv_tfs},
+        "fit_roofline": {"bound": "alu", "achieved": fit_tfs, "peak": fit_peak_tfs, "unit": "TFLOP/s",
+                         "frac": fit_tfs / fit_peak_tfs, "pairs": fit_pairs, "flops_per_pair": FIT_FLOPS_PER_PAIR,
+                         "pairs_per_s": fit_pairs / fit_s,
+                         "traffic": fit_prof["traffic_bytes_per_step"] if fit_prof else None,
+                         "kernel": "fit_batched_kernel (all sweeps + D, one launch)", "ms": fit_s * 1e3},
         "cpu_baseline": cpu,
         "cpu_context": cpu_context,
         "extras": extras,

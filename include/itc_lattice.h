@@ -217,6 +217,7 @@ itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t
  */
 size_t itc_lattice_literal_work_bytes(const itc_lattice_desc* d, int32_t M, double omega,
                                       int32_t radius_omega);
+
 itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weights, double omega,
                                    int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
                                    double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,
@@ -410,6 +411,9 @@ int32_t itc_lattice_plan_size(const itc_plan* p);
  *   before the change keeps the old launch shapes, so capture after tuning.
  */
 int32_t itc_lattice_plan_conv_classes(const itc_plan* p);
+/* Kernel launches of the plan's convolution (one per vector-ALU class, one for
+ * all matrix-core classes together); -1 if p is NULL. */
+int32_t itc_lattice_plan_conv_launches(const itc_plan* p);
 itc_status itc_lattice_plan_conv_class(const itc_plan* p, int32_t c, int32_t* key, int32_t* seg_rows,
                                        int32_t* blocks_per_cu, int32_t* max_blocks_per_cu);
 itc_status itc_lattice_plan_set_conv_shape(itc_plan* p, int32_t key, int32_t seg_rows, int32_t blocks_per_cu);

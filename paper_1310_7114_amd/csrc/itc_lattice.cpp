@@ -538,6 +538,8 @@ int32_t itc_lattice_plan_size(const itc_plan* p) { return p ? p->n : -1; }
 
 int32_t itc_lattice_plan_conv_classes(const itc_plan* p) { return p ? (int32_t)p->cls.size() : -1; }
 
+int32_t itc_lattice_plan_conv_launches(const itc_plan* p) { return p ? (int32_t)p->launch_key.size() : -1; }
+
 itc_status itc_lattice_plan_conv_class(const itc_plan* p, int32_t c, int32_t* key, int32_t* seg_rows,
                                        int32_t* blocks_per_cu, int32_t* max_blocks_per_cu) {
   if (!p) return fail(ITC_E_NULL, "plan is NULL");

@@ -87,6 +87,7 @@ SIGNATURES = {
     "itc_lattice_chamfer_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_conv_classes": (ctypes.c_int32, [_P]),
+    "itc_lattice_plan_conv_launches": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_conv_class": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "itc_lattice_plan_set_conv_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "itc_lattice_plan_destroy": (None, [_P]),
@@ -341,12 +342,6 @@ def label(weights: torch.Tensor, w: torch.Tensor, scale: float = 1.0, out: Optio
     return out[:, :W]
 
 
-def paper_widths(N: float, M: int):
-    """(xi, omega) of the paper's runtime experiments: omega = sqrt(N/M)/2, xi = omega/2."""
-    omega = (float(N) / M) ** 0.5 / 2.0
-    return omega / 2.0, omega
-
-
 def fit_literal(weights: torch.Tensor, w_init: torch.Tensor, xi: float, omega: float, iters: int,
                 theta: float = -1.0, scale: float = 1.0, radius_xi: int = 0, radius_omega: int = 0,
                 trace: bool = True, work: Optional[torch.Tensor] = None):
@@ -531,6 +526,10 @@ class BatchPlan:
             _check(lib.itc_lattice_plan_conv_class(self.handle, c, *[ctypes.byref(x) for x in v]))
             out.append(dict(zip(("key", "seg_rows", "blocks_per_cu", "max_blocks_per_cu"), (x.value for x in v))))
         return out
+
+    def conv_launches(self) -> int:
+        """Kernel launches of one `precompute` (one for all 8-bit images of aligned rows)."""
+        return int(load().itc_lattice_plan_conv_launches(self.handle))
 
     def set_conv_shape(self, key: int, seg_rows: int = 0, blocks_per_cu: int = 0):
         """Tile shape of one convolution class (0 = default); capture graphs after this."""
