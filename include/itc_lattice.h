@@ -218,6 +218,25 @@ itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t
 size_t itc_lattice_literal_work_bytes(const itc_lattice_desc* d, int32_t M, double omega,
                                       int32_t radius_omega);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Algorithm 1
+ * as itc_lattice_literal_fit, with the same arguments except `work`, which is
+ * replaced by a library-owned scratch array of ITC_LITERAL_SCRATCH_MIB MiB per
+ * GPU (held until the process ends; its address is looked up once per device
+ * at the first call there). No allocation, no hipFree and no allocating
+ * library routine on any call. Problems whose work memory
+ * (itc_lattice_literal_work_bytes) exceeds the array return ITC_E_UNSUPPORTED
+ * before anything is enqueued. Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other streams, other threads) race, so the
+ * caller serialises them; each call initialises what it reads. Same results
+ * as itc_lattice_literal_fit, bit for bit.
+ */
+#define ITC_LITERAL_SCRATCH_MIB 64
+itc_status itc_lattice_literal_fit_noalloc(const itc_lattice_desc* d, const void* weights, double omega,
+                                           int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                           double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,
+                                           void* stream);
 itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weights, double omega,
                                    int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
                                    double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "itc_lattice.h"
+
 namespace itc {
 
 // ---------------------------------------------------------------------------
@@ -172,6 +174,12 @@ struct LiteralArgs {
   int32_t* iters_done;  // or null
 };
 hipError_t launch_literal(const LiteralArgs& la, const int32_t* w_init, int32_t* w_out, hipStream_t s);
+// The body of itc_lattice_literal_fit with a work buffer of work_cap bytes
+// (host layer), and the host layer's error reporting.
+itc_status literal_fit_with_work(const itc_lattice_desc* d, const void* weights, double omega, int32_t radius_omega,
+                                 int32_t M, const int32_t* w_init, int32_t iters, double theta, int32_t* w_out,
+                                 double* d_trace, int32_t* iters_done, void* work, size_t work_cap, void* stream);
+itc_status report_error(itc_status s, const char* msg);
 
 // Chamfer transform: a task is (image, strip) for the column pass and
 // (image, first row) for the row pass.

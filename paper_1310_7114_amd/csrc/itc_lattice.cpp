@@ -694,10 +694,15 @@ size_t itc_lattice_literal_work_bytes(const itc_lattice_desc* d, int32_t M, doub
   return L.total;
 }
 
-itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weights, double omega,
-                                   int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
-                                   double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
-                                   void* stream) {
+}  // extern "C"
+
+// Algorithm 1 with a work buffer of `work_cap` bytes (the caller's, of the
+// size itc_lattice_literal_work_bytes gives, or the library's static
+// scratch); ITC_E_UNSUPPORTED when the problem needs more.
+itc_status itc::literal_fit_with_work(const itc_lattice_desc* d, const void* weights, double omega,
+                                      int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                      double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
+                                      size_t work_cap, void* stream) {
   int R = 0, rc = 0;
   itc_status st = check_desc(d, &R, &rc);
   if (st != ITC_OK) return st;
@@ -713,6 +718,9 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
   if (!literal_layout(*d, M, omega, radius_omega, L))
     return fail(radius_omega < 0 ? ITC_E_ARG : ITC_E_UNSUPPORTED, "omega window radius must be 1..%d",
                 ITC_MAX_LITERAL_RADIUS);
+  if (L.total > work_cap)
+    return fail(ITC_E_UNSUPPORTED, "the problem needs %zu bytes of work memory, more than the %zu available",
+                L.total, work_cap);
   ImageDesc im = make_image(*d, R, rc);
   hipStream_t s = (hipStream_t)stream;
   char* wb = (char*)work;
@@ -738,6 +746,18 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
   e = itc::launch_literal(la, w_init, w_out, s);
   if (e != hipSuccess) return device_fail(e, "Algorithm 1 launch");
   return ok();
+}
+
+itc_status itc::report_error(itc_status s, const char* msg) { return fail(s, "%s", msg); }
+
+extern "C" {
+
+itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weights, double omega,
+                                   int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                   double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
+                                   void* stream) {
+  return itc::literal_fit_with_work(d, weights, omega, radius_omega, M, w_init, iters, theta, w_out, d_trace,
+                                    iters_done, work, SIZE_MAX, stream);
 }
 
 itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,

@@ -241,3 +241,46 @@ hipError_t launch_literal(const LiteralArgs& la, const int32_t* w_init, int32_t*
 }
 
 }  // namespace itc
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 without a caller work buffer: the work memory is a file-scope
+// device array, one per GPU, held until the process ends. Its address on the
+// current device is taken with hipGetSymbolAddress at the first call on that
+// device (the array's name in host code is not a device address).
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+namespace itc {
+namespace {
+
+constexpr size_t LITERAL_SCRATCH_BYTES = (size_t)ITC_LITERAL_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[LITERAL_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+}  // namespace
+}  // namespace itc
+
+extern "C" itc_status itc_lattice_literal_fit_noalloc(const itc_lattice_desc* d, const void* weights, double omega,
+                                                      int32_t radius_omega, int32_t M, const int32_t* w_init,
+                                                      int32_t iters, double theta, int32_t* w_out, double* d_trace,
+                                                      int32_t* iters_done, void* stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= itc::MAX_DEVICES)
+    return itc::report_error(ITC_E_DEVICE, "no current HIP device");
+  void* work = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(itc::g_scratch_mu);
+    if (!itc::g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(itc::scratch));
+      if (e != hipSuccess || !p) return itc::report_error(ITC_E_DEVICE, "hipGetSymbolAddress of the scratch array failed");
+      itc::g_scratch_ptr[dev] = p;
+    }
+    work = itc::g_scratch_ptr[dev];
+  }
+  return itc::literal_fit_with_work(d, weights, omega, radius_omega, M, w_init, iters, theta, w_out, d_trace,
+                                    iters_done, work, itc::LITERAL_SCRATCH_BYTES, stream);
+}

@@ -84,6 +84,8 @@ SIGNATURES = {
     "itc_lattice_literal_work_bytes": (ctypes.c_size_t, [_DP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
     "itc_lattice_literal_fit": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P,
                                                ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
+    "itc_lattice_literal_fit_noalloc": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                                       _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P]),
     "itc_lattice_chamfer_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_conv_classes": (ctypes.c_int32, [_P]),
@@ -367,6 +369,32 @@ def fit_literal(weights: torch.Tensor, w_init: torch.Tensor, xi: float, omega: f
                                           _ptr(w_init), int(iters), float(theta), _ptr(w_out), _ptr(d_trace),
                                           _ptr(done), _ptr(work), _stream()))
     return w_out, d_trace, done
+
+
+def fit_literal_noalloc(weights: torch.Tensor, w_init: torch.Tensor, xi: float, omega: float, iters: int,
+                        theta: float = -1.0, scale: float = 1.0, radius_xi: int = 0, radius_omega: int = 0,
+                        trace: bool = True, w_out: Optional[torch.Tensor] = None, d_trace: Optional[torch.Tensor] = None,
+                        done: Optional[torch.Tensor] = None):
+    """fit_literal through the entry point that allocates nothing (the library's static work array);
+    pass w_out, d_trace and done to make the call itself allocation-free."""
+    if weights.dim() != 2:
+        raise ValueError("weights must be (H, W)")
+    if weights.stride(1) != 1:
+        weights = weights.contiguous()
+    H, W = weights.shape
+    desc = make_desc(H, W, xi, weights.dtype, torch.float32, scale, radius_xi, pitch=weights.stride(0))
+    w_init = w_init.to(torch.int32).contiguous()
+    M = int(w_init.shape[0])
+    if w_out is None:
+        w_out = torch.empty_like(w_init)
+    if trace and d_trace is None:
+        d_trace = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=weights.device)
+    if done is None:
+        done = torch.zeros(1, dtype=torch.int32, device=weights.device)
+    _check(load().itc_lattice_literal_fit_noalloc(ctypes.byref(desc), _ptr(weights), float(omega), int(radius_omega),
+                                                  M, _ptr(w_init), int(iters), float(theta), _ptr(w_out),
+                                                  _ptr(d_trace if trace else None), _ptr(done), _stream()))
+    return w_out, (d_trace if trace else None), done
 
 
 # ---------------------------------------------------------------------------
