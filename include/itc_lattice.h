@@ -290,7 +290,7 @@ typedef struct {
   int32_t radius;               /* R; 0 => ceil(3 sigma); at most ITC_MAX_VOLUME_RADIUS */
   int64_t row_pitch;            /* elements between rows of the weights (>= width)   */
   int64_t slice_pitch;          /* elements between slices (>= height * row_pitch)  */
-  itc_dtype weight_dtype;       /* ITC_U8 | ITC_F32 | ITC_F64                        */
+  int32_t weight_dtype;         /* itc_dtype: ITC_U8 | ITC_F32 | ITC_F64 (int32_t, so any value can be checked) */
   int32_t reserved;             /* must be 0                                         */
   double weight_scale;          /* h = weight_scale * stored                         */
   double sigma;                 /* kernel width (> 0)                                */
@@ -362,17 +362,27 @@ itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void
 /*
  * Fit of every image (one persistent launch), then D at its final codebook.
  * Writes w_out (same offsets as w_init; may alias), s_x[i] and d_out[i]
- * (double [n], each may be NULL), iters_done[i] (int32 [n], may be NULL).
+ * (double [n], each may be NULL), iters_done[i] (int32 [n], may be NULL) and
+ * status[i] (int32 [n], may be NULL): 0, or the sum of
+ *   ITC_FIT_NONFINITE_SUMS  S_XW or S_W was not finite (non-finite weights or
+ *                           maps): the image's sweeps stopped there and w_out
+ *                           holds its last codebook, all of whose sums were
+ *                           finite before; iters_done counts the sweeps done;
+ *   ITC_FIT_NONFINITE_STEP  some codevector step was not finite;
+ *   ITC_FIT_NONFINITE_D     D at the final codebook is not finite.
  * theta applies to every image (< 0: run all sweeps).
  */
+#define ITC_FIT_NONFINITE_SUMS 1
+#define ITC_FIT_NONFINITE_STEP 2
+#define ITC_FIT_NONFINITE_D 4
 itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_init, double theta,
                                    void* w_out, double* s_x, double* d_out, int32_t* iters_done,
-                                   void* stream);
+                                   int32_t* status, void* stream);
 
 /* itc_lattice_precompute_batched followed by itc_lattice_fit_batched. */
 itc_status itc_lattice_run_batched(itc_plan* p, const void* weights, void* maps, const void* w_init,
                                    double theta, void* w_out, double* s_x, double* d_out,
-                                   int32_t* iters_done, void* stream);
+                                   int32_t* iters_done, int32_t* status, void* stream);
 
 /*
  * Adjoint of the divergence of every image at codebooks `w` (same layout as

@@ -472,3 +472,58 @@ hipError_t launch_sx_finalize(const ImageDesc& img, const void* maps, double* s_
 }
 
 }  // namespace itc
+
+// ---------------------------------------------------------------------------
+// Debug validation: count the non-finite stored weights of images (FP32 or
+// FP64 weights; 8-bit weights are always finite) into a device counter.
+// ---------------------------------------------------------------------------
+namespace itc {
+namespace {
+
+__device__ unsigned int g_nonfinite_count;
+
+template <typename WT>
+__device__ void count_nonfinite(const ImageDesc& im, const char* wbase) {
+  const WT* w = reinterpret_cast<const WT*>(wbase + im.weight_off);
+  unsigned int n = 0;
+  const int64_t total = (int64_t)im.H * im.W;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = i / im.W, v = i - u * im.W;
+    n += isfinite((double)w[u * im.pitch + v]) ? 0u : 1u;
+  }
+  if (n) atomicAdd(&g_nonfinite_count, n);
+}
+
+__global__ void nonfinite_images_kernel(const ImageDesc* __restrict__ images, int n, const char* wbase) {
+  for (int k = 0; k < n; ++k) {
+    const ImageDesc im = images[k];
+    if (im.wdtype == 1) count_nonfinite<float>(im, wbase);
+    if (im.wdtype == 2) count_nonfinite<double>(im, wbase);
+  }
+}
+
+__global__ void nonfinite_image_kernel(ImageDesc im, const char* wbase) {
+  if (im.wdtype == 1) count_nonfinite<float>(im, wbase);
+  if (im.wdtype == 2) count_nonfinite<double>(im, wbase);
+}
+
+}  // namespace
+
+hipError_t count_nonfinite_weights(const ImageDesc* h_image, const ImageDesc* d_images, int n, const void* w,
+                                   unsigned int* count, hipStream_t s) {
+  const unsigned int zero = 0;
+  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_nonfinite_count), &zero, sizeof zero, 0,
+                                        hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  if (h_image)
+    hipLaunchKernelGGL(nonfinite_image_kernel, dim3(256), dim3(256), 0, s, *h_image, (const char*)w);
+  else
+    hipLaunchKernelGGL(nonfinite_images_kernel, dim3(256), dim3(256), 0, s, d_images, n, (const char*)w);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyFromSymbolAsync(count, HIP_SYMBOL(g_nonfinite_count), sizeof *count, 0, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace itc

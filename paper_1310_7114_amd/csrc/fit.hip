@@ -34,6 +34,11 @@ constexpr uint32_t FIT_OOB = 0x80000000u;
 
 using P2 = V2<double>;
 
+// Per-image status bits (the batched fit's status output).
+constexpr int32_t FIT_STATUS_SUMS = 1;  // S_XW or S_W not finite: the fit stopped at the last finite codebook
+constexpr int32_t FIT_STATUS_W = 2;     // a codevector step was not finite
+constexpr int32_t FIT_STATUS_D = 4;     // D not finite
+
 __device__ __forceinline__ float exp2_neg(float x) { return __builtin_amdgcn_exp2f(-x); }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
@@ -60,6 +65,7 @@ struct FitImageArgs {
   double* d_trace;   // [iters+1] or null
   double* d_out;     // one double or null
   int32_t* iters_done;
+  int32_t* status;   // FIT_STATUS_* bits of this image, or null
   double theta;
   bool write_w;
   void* grad_w;          // gradient mode: dL/dw [M][2] at w_init (no update)
@@ -114,7 +120,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   const int H = im.H, W = im.W;
   const uint32_t planeb = (uint32_t)(im.plane * (int64_t)sizeof(T));
   const rsrc_t mres = make_rsrc(a.mbase + im.map_off, 3u * planeb);
-  const bool need_d = a.d_trace != nullptr || a.d_out != nullptr;
+  const bool need_d = a.d_trace != nullptr || a.d_out != nullptr || a.status != nullptr;
   // corner values of the cell each owned codevector was last read in (key -2: none yet)
   int cell[MAXPASS];
   T cav[MAXPASS][4], cmu[MAXPASS][4], cmv[MAXPASS][4];
@@ -127,6 +133,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
   const Q2* wcol = Wh + p;  // this lane's column of the pair loop: j = p + P t
 
   bool stop = false;
+  int32_t flags = 0;   // status bits (uniform except FIT_STATUS_W, combined at the end)
   int t = 0;
   for (;; ++t) {
     const bool last = (t == im.iters) || stop;
@@ -252,10 +259,15 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       S_XW += red[2 * w];
       S_W += red[2 * w + 1];
     }
-    if (tid == 0 && (a.d_trace || (last && a.d_out))) {
+    // non-finite sums (non-finite weights or maps) end the fit at this codebook
+    const bool sums_ok = isfinite(S_XW) && isfinite(S_W);  // uniform
+    const bool final_eval = last || !sums_ok;
+    if (!sums_ok) flags |= FIT_STATUS_SUMS;
+    if (tid == 0 && (a.d_trace || (final_eval && a.d_out) || a.status)) {
       const double D = log(S_W) + log(a.s_x) - 2.0 * log(S_XW);
+      if (!isfinite(D)) flags |= FIT_STATUS_D;
       if (a.d_trace) a.d_trace[t] = D;
-      if (last && a.d_out) *a.d_out = D;
+      if (final_eval && a.d_out) *a.d_out = D;
     }
     if (a.grad_w) {  // adjoint of D at this codebook (eq. (1) differentiated through the reads)
       const double gd = *a.grad_d;
@@ -270,7 +282,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       }
       break;
     }
-    if (last) break;
+    if (final_eval) break;
 
     // ---- Jacobi update of every owned codevector (all P lanes alike) ----
     // c / s (E = E' / s), in the map type
@@ -288,6 +300,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
           const T inv = recip(Ak[ps]);
           const T du = (gu[ps] - cs * Eu[ps]) * inv;
           const T dv = (gv[ps] - cs * Ev[ps]) * inv;
+          if (!isfinite(du) || !isfinite(dv)) flags |= FIT_STATUS_W;
           wu[ps] += (double)du;
           wv[ps] += (double)dv;
           if (a.theta >= 0.0) step = fmaxf(step, (float)sqrt((double)du * du + (double)dv * dv));
@@ -317,6 +330,10 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     }
   }
   if (tid == 0 && a.iters_done) *a.iters_done = t;
+  if (a.status) {
+    const int32_t any_w = __syncthreads_or((flags & FIT_STATUS_W) != 0);
+    if (tid == 0) *a.status = (flags & ~FIT_STATUS_W) | (any_w ? FIT_STATUS_W : 0);
+  }
   __syncthreads();  // shared memory is reused by the next image
 }
 
@@ -355,6 +372,7 @@ __global__ void __launch_bounds__(FIT_NT) fit_image_kernel(ImageDesc im, FitArgs
   a.d_trace = fa.d_trace;
   a.d_out = fa.d_out;
   a.iters_done = fa.iters_done;
+  a.status = nullptr;
   a.theta = fa.theta;
   a.write_w = fa.write_w != 0;
   a.grad_w = fa.grad_w;
@@ -383,6 +401,7 @@ __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __
     a.d_trace = nullptr;
     a.d_out = fa.d_out ? fa.d_out + i : nullptr;
     a.iters_done = fa.iters_done ? fa.iters_done + i : nullptr;
+    a.status = fa.status ? fa.status + i : nullptr;
     a.theta = fa.theta;
     a.write_w = fa.write_w != 0;
     a.grad_w = fa.grad_w;

@@ -128,6 +128,11 @@ hipError_t launch_conv_mx_image(const ImageDesc& h_image, const void* weights, v
 hipError_t launch_conv_mx_tiles(int max_ra, const ImageDesc* d_images, const ConvTile* d_tiles, const XcdSplit& xs,
                                 const void* weights, void* maps, int grid, hipStream_t s);
 int conv_mx_blocks_per_cu(int max_ra);
+// Debug validation (ITC_DEBUG_VALIDATE): the number of non-finite stored
+// weights of one image (h_image) or of n plan images (d_images); waits for
+// the stream.
+hipError_t count_nonfinite_weights(const ImageDesc* h_image, const ImageDesc* d_images, int n, const void* w,
+                                   unsigned int* count, hipStream_t s);
 // S_X of one image: the fixed-order sum of its FP64 partials.
 hipError_t launch_sx_finalize(const ImageDesc& img, const void* maps, double* s_x, hipStream_t s);
 // 3-D lattices: one volume (slice, row, column) and its window radius.
@@ -207,6 +212,7 @@ struct FitArgs {
   double* d_trace;       // single image: [iters+1] or null
   double* d_out;         // [n] or null
   int32_t* iters_done;   // [n] or null
+  int32_t* status;       // [n] status bits per image, or null (batched only)
   double theta;
   int32_t n;             // images
   int32_t m_max;         // largest M (sizes the shared memory)

@@ -1,13 +1,16 @@
 // C-ABI host layer of the lattice ITC library: argument validation, image
 // descriptors, batch plans and kernel launches. No allocation happens on the
 // per-call paths; plans allocate their device descriptor arrays once.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -42,6 +45,56 @@ itc_status device_fail(hipError_t e, const char* where) {
 }
 
 size_t real_size(int dt) { return dt == ITC_F64 ? 8 : 4; }
+
+bool env_flag(const char* name) {
+  const char* v = std::getenv(name);
+  return v && *v && std::strcmp(v, "0") != 0;
+}
+
+// ITC_DEBUG_VALIDATE: the precompute calls scan FP32/FP64 weights for
+// non-finite values first (a synchronous kernel) and reject them.
+bool debug_validate() {
+  static const bool on = env_flag("ITC_DEBUG_VALIDATE");
+  return on;
+}
+
+// ITC_TRACE: every entry point opens a roctx range named after it (shown by
+// rocprofv3 --marker-trace). The roctx library is opened only then.
+using roctx_push_t = int (*)(const char*);
+using roctx_pop_t = int (*)();
+roctx_push_t g_roctx_push = nullptr;
+roctx_pop_t g_roctx_pop = nullptr;
+
+bool trace_on() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    if (!env_flag("ITC_TRACE")) return;
+    for (const char* lib : {"librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so", "libroctx64.so.4"}) {
+      void* h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+      if (!h) continue;
+      g_roctx_push = reinterpret_cast<roctx_push_t>(dlsym(h, "roctxRangePushA"));
+      g_roctx_pop = reinterpret_cast<roctx_pop_t>(dlsym(h, "roctxRangePop"));
+      if (g_roctx_push && g_roctx_pop) return;
+      g_roctx_push = nullptr;
+      g_roctx_pop = nullptr;
+    }
+  });
+  return g_roctx_push != nullptr;
+}
+
+struct TraceRange {
+  bool on;
+  explicit TraceRange(const char* name) : on(trace_on()) {
+    if (on) g_roctx_push(name);
+  }
+  ~TraceRange() {
+    if (on) g_roctx_pop();
+  }
+};
+
+// Rejects FP32/FP64 weights holding a non-finite value when ITC_DEBUG_VALIDATE is set.
+itc_status validate_weights(const ImageDesc* h_image, const ImageDesc* d_images, int n, bool any_float,
+                            const void* weights, hipStream_t s);
 
 int effective_radius(const itc_lattice_desc& d) {
   if (d.radius > 0) return d.radius;
@@ -120,6 +173,16 @@ ImageDesc make_image(const itc_lattice_desc& d, int R, int rc) {
 }
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+itc_status validate_weights(const ImageDesc* h_image, const ImageDesc* d_images, int n, bool any_float,
+                            const void* weights, hipStream_t s) {
+  if (!debug_validate() || !any_float) return ITC_OK;
+  unsigned int count = 0;
+  const hipError_t e = itc::count_nonfinite_weights(h_image, d_images, n, weights, &count, s);
+  if (e != hipSuccess) return device_fail(e, "weight validation");
+  if (count) return fail(ITC_E_ARG, "the weights hold %u non-finite values (ITC_DEBUG_VALIDATE)", count);
+  return ITC_OK;
+}
 
 int device_cus() {
   int dev = 0, n = 0;
@@ -311,6 +374,7 @@ size_t itc_lattice_maps_bytes(const itc_lattice_desc* d) {
 
 itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights, void* maps, double* s_x,
                                   void* stream) {
+  TraceRange trace_range("itc_lattice_precompute");
   int R = 0, rc = 0;
   itc_status st = check_desc(d, &R, &rc);
   if (st != ITC_OK) return st;
@@ -319,6 +383,8 @@ itc_status itc_lattice_precompute(const itc_lattice_desc* d, const void* weights
   const bool f64 = d->real_dtype == ITC_F64;
   const ImageDesc im = make_image(*d, R, rc);
   hipStream_t s = (hipStream_t)stream;
+  st = validate_weights(&im, nullptr, 1, d->weight_dtype != ITC_U8, weights, s);
+  if (st != ITC_OK) return st;
   hipError_t e = itc::launch_conv_image(f64, im, weights, maps, s);
   if (e != hipSuccess) return device_fail(e, "convolution launch");
   e = itc::launch_sx_finalize(im, maps, s_x, s);
@@ -364,11 +430,13 @@ static itc_status fit_common(const itc_lattice_desc* d, const void* maps, const 
 itc_status itc_lattice_fit(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
                            const void* w_init, int32_t iters, double theta, void* w_out, double* d_trace,
                            int32_t* iters_done, void* stream) {
+  TraceRange trace_range("itc_lattice_fit");
   return fit_common(d, maps, s_x, M, w_init, iters, theta, w_out, d_trace, nullptr, iters_done, true, stream);
 }
 
 itc_status itc_lattice_divergence(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
                                   const void* w, double* d_out, void* stream) {
+  TraceRange trace_range("itc_lattice_divergence");
   if (!d_out) return fail(ITC_E_NULL, "d_out must be non-NULL");
   if (!s_x) return fail(ITC_E_NULL, "s_x must be non-NULL");
   return fit_common(d, maps, s_x, M, w, 0, -1.0, nullptr, nullptr, d_out, nullptr, false, stream);
@@ -377,6 +445,7 @@ itc_status itc_lattice_divergence(const itc_lattice_desc* d, const void* maps, c
 itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void* maps, const double* s_x,
                                            int32_t M, const void* w, const double* grad_d, void* grad_w,
                                            void* grad_weights, void* stream) {
+  TraceRange trace_range("itc_lattice_divergence_backward");
   int R = 0, rc = 0;
   itc_status st = check_desc(d, &R, &rc);
   if (st != ITC_OK) return st;
@@ -422,6 +491,7 @@ itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void
 // batched
 // ---------------------------------------------------------------------------
 itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
+  TraceRange trace_range("itc_lattice_plan_create");
   if (!b || !out) return fail(ITC_E_NULL, "batch and out must be non-NULL");
   *out = nullptr;
   if (b->n < 1) return fail(ITC_E_ARG, "batch must hold >= 1 image (got %d)", b->n);
@@ -574,6 +644,7 @@ itc_status itc_lattice_plan_set_conv_shape(itc_plan* p, int32_t key, int32_t seg
 itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps, const double* s_x, const void* w,
                                                    const double* grad_d, void* grad_w, void* grad_weights,
                                                    void* stream) {
+  TraceRange trace_range("itc_lattice_divergence_backward_batched");
   if (!p || !maps || !w || !grad_d) return fail(ITC_E_NULL, "plan, maps, w and grad_d must be non-NULL");
   if (grad_weights && !s_x) return fail(ITC_E_NULL, "s_x is required for grad_weights");
   if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
@@ -621,10 +692,13 @@ void itc_lattice_plan_destroy(itc_plan* p) {
 }
 
 itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void* maps, void* stream) {
+  TraceRange trace_range("itc_lattice_precompute_batched");
   if (!p || !weights || !maps) return fail(ITC_E_NULL, "plan, weights and maps must be non-NULL");
   if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
   if (p->any_mx && (uintptr_t)weights % 4 != 0)
     return fail(ITC_E_ARG, "8-bit weights must be 4-byte aligned (the images' offsets and pitches are)");
+  const itc_status vs = validate_weights(nullptr, p->d_images, p->n, !p->all_u8, weights, (hipStream_t)stream);
+  if (vs != ITC_OK) return vs;
   for (size_t l = 0; l < p->launch_key.size(); ++l) {
     const int key = p->launch_key[l];
     hipError_t e =
@@ -640,7 +714,8 @@ itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void
 }
 
 itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_init, double theta, void* w_out,
-                                   double* s_x, double* d_out, int32_t* iters_done, void* stream) {
+                                   double* s_x, double* d_out, int32_t* iters_done, int32_t* status, void* stream) {
+  TraceRange trace_range("itc_lattice_fit_batched");
   if (!p || !maps || !w_init || !w_out) return fail(ITC_E_NULL, "plan, maps, w_init and w_out must be non-NULL");
   if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
   if (!aligned256(maps)) return fail(ITC_E_ARG, "maps must be 256-byte aligned");
@@ -652,6 +727,7 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
   a.s_x_out = s_x;
   a.d_out = d_out;
   a.iters_done = iters_done;
+  a.status = status;
   a.theta = theta;
   a.n = p->n;
   a.m_max = p->m_max;
@@ -703,6 +779,7 @@ itc_status itc::literal_fit_with_work(const itc_lattice_desc* d, const void* wei
                                       int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
                                       double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
                                       size_t work_cap, void* stream) {
+  TraceRange trace_range("itc_lattice_literal_fit");
   int R = 0, rc = 0;
   itc_status st = check_desc(d, &R, &rc);
   if (st != ITC_OK) return st;
@@ -762,6 +839,7 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
 
 itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,
                              int32_t* labels, void* stream) {
+  TraceRange trace_range("itc_lattice_label");
   int R = 0, rc = 0;
   itc_status st = check_desc(d, &R, &rc, false);
   if (st != ITC_OK) return st;
@@ -776,6 +854,7 @@ itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int
 
 itc_status itc_lattice_label_batched(itc_plan* p, const void* weights, const void* w, int32_t* labels,
                                      void* stream) {
+  TraceRange trace_range("itc_lattice_label_batched");
   if (!p || !weights || !w || !labels) return fail(ITC_E_NULL, "plan, weights, w and labels must be non-NULL");
   if (itc::label_rows_per_task() != itc::chamfer_rows_per_task())
     return fail(ITC_E_DEVICE, "row groups of the labelling and the chamfer pass differ");
@@ -852,6 +931,7 @@ size_t itc_lattice_recursive_work_bytes(const itc_lattice_desc* d) {
 
 itc_status itc_lattice_precompute_recursive(const itc_lattice_desc* d, const void* weights, void* maps,
                                             double* s_x, void* work, void* stream) {
+  TraceRange trace_range("itc_lattice_precompute_recursive");
   int R = 0, rc = 0;
   itc_status st = check_recursive(d, &R, &rc);
   if (st != ITC_OK) return st;
@@ -926,6 +1006,7 @@ size_t itc_volume_work_bytes(const itc_volume_desc* d) {
 
 itc_status itc_volume_precompute(const itc_volume_desc* d, const void* weights, void* maps, double* s_x,
                                  void* work, void* stream) {
+  TraceRange trace_range("itc_volume_precompute");
   itc::VolumeGeom vg;
   itc_status st = check_volume(d, &vg);
   if (st != ITC_OK) return st;
@@ -941,6 +1022,7 @@ itc_status itc_volume_precompute(const itc_volume_desc* d, const void* weights, 
 itc_status itc_volume_fit(const itc_volume_desc* d, const void* maps, const double* s_x, int32_t M,
                           const float* w_init, int32_t iters, double theta, float* w_out, double* d_trace,
                           int32_t* iters_done, void* stream) {
+  TraceRange trace_range("itc_volume_fit");
   itc::VolumeGeom vg;
   itc_status st = check_volume(d, &vg);
   if (st != ITC_OK) return st;
@@ -964,6 +1046,7 @@ static itc_status check_chamfer_mask(int32_t a, int32_t b) {
 
 itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t a, int32_t b, float* t_out,
                                void* stream) {
+  TraceRange trace_range("itc_lattice_chamfer");
   if (!d || !x || !t_out) return fail(ITC_E_NULL, "desc, x and t_out must be non-NULL");
   if (d->height < 1 || d->width < 1) return fail(ITC_E_ARG, "height and width must be >= 1");
   if (d->pitch < d->width) return fail(ITC_E_ARG, "pitch %lld < width %d", (long long)d->pitch, d->width);
@@ -986,6 +1069,7 @@ itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t
 
 itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t a, int32_t b, float* t_out,
                                        void* stream) {
+  TraceRange trace_range("itc_lattice_chamfer_batched");
   if (!p || !weights || !t_out) return fail(ITC_E_NULL, "plan, weights and t_out must be non-NULL");
   if (!p->all_u8) return fail(ITC_E_ARG, "the chamfer transform takes ITC_U8 images");
   if (p->w_max > ITC_MAX_CHAMFER_WIDTH)
@@ -1003,10 +1087,11 @@ itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t
 }
 
 itc_status itc_lattice_run_batched(itc_plan* p, const void* weights, void* maps, const void* w_init, double theta,
-                                   void* w_out, double* s_x, double* d_out, int32_t* iters_done, void* stream) {
+                                   void* w_out, double* s_x, double* d_out, int32_t* iters_done, int32_t* status,
+                                   void* stream) {
   itc_status st = itc_lattice_precompute_batched(p, weights, maps, stream);
   if (st != ITC_OK) return st;
-  return itc_lattice_fit_batched(p, maps, w_init, theta, w_out, s_x, d_out, iters_done, stream);
+  return itc_lattice_fit_batched(p, maps, w_init, theta, w_out, s_x, d_out, iters_done, status, stream);
 }
 
 }  // extern "C"

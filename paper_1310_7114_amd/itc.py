@@ -16,9 +16,11 @@ from typing import Optional, Sequence
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libitc_lattice.so")
+# the in-tree library; ITC_LIB_PATH names another build of it (the host-sanitized one of the ABI tests)
+LIB_PATH = os.environ.get("ITC_LIB_PATH") or os.path.join(_PKG, "libitc_lattice.so")
 
 ITC_U8, ITC_F32, ITC_F64 = 0, 1, 2
+ITC_FIT_NONFINITE_SUMS, ITC_FIT_NONFINITE_STEP, ITC_FIT_NONFINITE_D = 1, 2, 4
 ITC_MAX_CODEVECTORS = 1024
 STATUS = {0: "ITC_OK", 1: "ITC_E_NULL", 2: "ITC_E_ARG", 3: "ITC_E_UNSUPPORTED", 4: "ITC_E_DEVICE"}
 
@@ -67,8 +69,8 @@ SIGNATURES = {
     "itc_lattice_divergence_backward": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "itc_lattice_plan_create": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_void_p)]),
     "itc_lattice_precompute_batched": (ctypes.c_int, [_P, _P, _P, _P]),
-    "itc_lattice_fit_batched": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
-    "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P]),
+    "itc_lattice_fit_batched": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P]),
+    "itc_lattice_run_batched": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _P, _P]),
     "itc_lattice_divergence_backward_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer": (ctypes.c_int, [_DP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_label": (ctypes.c_int, [_DP, _P, ctypes.c_int32, _P, _P, _P]),
@@ -569,17 +571,18 @@ class BatchPlan:
                                                      _ptr(self.maps if maps is None else maps), _stream()))
 
     def fit(self, w_init: torch.Tensor, w_out: torch.Tensor, s_x=None, d_out=None, iters_done=None,
-            theta: float = -1.0, maps=None):
+            theta: float = -1.0, maps=None, status=None):
+        """Fit of every image; `status` (int32 [n]) receives the ITC_FIT_NONFINITE_* bits per image."""
         _check(load().itc_lattice_fit_batched(self.handle, _ptr(self.maps if maps is None else maps), _ptr(w_init),
                                               float(theta), _ptr(w_out), _ptr(s_x), _ptr(d_out), _ptr(iters_done),
-                                              _stream()))
+                                              _ptr(status), _stream()))
 
     def run(self, w_init: torch.Tensor, w_out: torch.Tensor, s_x=None, d_out=None, iters_done=None,
-            theta: float = -1.0, weights=None, maps=None):
+            theta: float = -1.0, weights=None, maps=None, status=None):
         _check(load().itc_lattice_run_batched(self.handle, _ptr(self._w(weights)),
                                               _ptr(self.maps if maps is None else maps), _ptr(w_init),
                                               float(theta), _ptr(w_out), _ptr(s_x), _ptr(d_out),
-                                              _ptr(iters_done), _stream()))
+                                              _ptr(iters_done), _ptr(status), _stream()))
 
     def backward(self, w: torch.Tensor, s_x: torch.Tensor, grad_d: torch.Tensor, grad_w=None, grad_weights=None,
                  maps=None):

@@ -100,7 +100,7 @@ def test_null_and_range_arguments(itc):
     assert fit(ctypes.byref(d), P, None, 4, P, 3, -1.0, P, P, None, None) == 1           # trace needs s_x
     assert fit(ctypes.byref(d), None, P, 4, P, 3, -1.0, P, None, None, None) == 1
     assert lib.itc_lattice_divergence(ctypes.byref(d), P, P, 4, P, None, None) == 1
-    assert lib.itc_lattice_fit_batched(None, P, P, -1.0, P, None, None, None, None) == 1
+    assert lib.itc_lattice_fit_batched(None, P, P, -1.0, P, None, None, None, None, None) == 1
     assert lib.itc_lattice_plan_size(None) == -1
     lib.itc_lattice_plan_destroy(None)
     # autotuning hooks of the convolution's tile shapes

@@ -1,5 +1,6 @@
 """Batched persistent form vs the per-image calls and the oracle (config 3)."""
 import json
+import math
 import os
 
 import numpy as np
@@ -220,6 +221,83 @@ def test_full_batch_maps_largest_per_sigma(gpu_lib):
         for g, r in zip(got, ref):
             assert float(np.abs(g - r).max() / np.abs(r).max()) <= 1e-5, (i, sigma)
         assert float(sx[i]) == pytest.approx(float(np.sum(c.weights * A)), rel=1e-6)
+
+
+def oracle_accepts(c, wg, W_ref, D_ref, k, maps):
+    """On an ill-conditioned image whose GPU codebook wg (after k sweeps) is farther than 1e-3 px from
+    the oracle's W_ref: the oracle's D at wg within 1e-5 max(1, |D|) of D_ref, and one oracle sweep
+    from wg no longer than 1.05 times the oracle's own last sweep plus 1e-4 px."""
+    d_at = O.lattice_divergence(c.weights, maps, wg, c.sigma)
+    w1 = O.fit_lattice(c.weights, wg, c.sigma, c.R, 1, maps=maps)[0]
+    W_prev = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, k - 1, maps=maps)[0]
+    step_gpu = float(np.linalg.norm(w1 - wg, axis=1).max())
+    step_last = float(np.linalg.norm(W_ref - W_prev, axis=1).max())
+    return abs(d_at - D_ref) <= 1e-5 * max(1.0, abs(D_ref)) and step_gpu <= 1.05 * step_last + 1e-4
+
+
+def test_batched_theta_stop_against_oracle(gpu_lib):
+    """The batched theta stop (stop after the first sweep whose largest codevector step is <= theta)
+    against the oracle's rule on 40 silhouettes: the same sweep count, except where the deciding step
+    lies within 1e-3 theta of theta (FP32 rounding may then decide either way, by one sweep), and the
+    codebooks within 1e-3 px where the counts agree (or, on the ill-conditioned images of the batch, a
+    codebook the oracle's iteration accepts, as in test_full_batch_codebooks_every_image)."""
+    theta = 0.05
+    cases = S.config3_cases(indices=range(200, 240))
+    plan, w0 = make_plan(gpu_lib, cases)
+    w, sx, d, done = run_plan(plan, w0, theta=theta)
+    stopped = 0
+    for i, c in enumerate(cases):
+        W_ref, tr_ref, done_ref, maps = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, c.iters, theta=theta)
+        k = int(done[i])
+        stopped += k < c.iters
+        if k != done_ref:
+            assert abs(k - done_ref) == 1, (i, k, done_ref)
+            # the oracle's step at the earlier of the two sweeps decides: it must be a near-tie
+            Wa = O.fit_lattice(c.weights, c.w0, c.sigma, c.R, min(k, done_ref) - 1, maps=maps)[0]
+            Wb = O.fit_lattice(c.weights, Wa, c.sigma, c.R, 1, maps=maps)[0]
+            step = float(np.linalg.norm(Wb - Wa, axis=1).max())
+            assert abs(step - theta) <= 1e-3 * theta, (i, step)
+            continue
+        got = plan.unpack(w, i).cpu().double().numpy()
+        if np.linalg.norm(got - W_ref, axis=1).max() > 1e-3:  # an ill-conditioned image (see above)
+            assert oracle_accepts(c, got, W_ref, tr_ref[-1], k, maps), (i, c.sigma, c.M)
+        assert abs(float(d[i]) - tr_ref[-1]) <= 1e-5 * max(1.0, abs(tr_ref[-1])), i
+    assert stopped >= 5  # the stop is exercised
+
+
+def test_batched_status_flags_nonfinite_weights(gpu_lib):
+    """FP32 weights with a NaN under a codevector of one image: that image's status has the non-finite-sums bit, its fit
+    stops at once (iters_done 0, w_out the initial codebook) with D not finite; the other images are
+    untouched (status 0, the same results as without the bad image)."""
+    cases = S.config3_cases(indices=range(300, 306))
+    imgs = [torch.from_numpy(c.img.astype(np.float32)) for c in cases]
+    def plan_of(images):
+        p = gpu_lib.BatchPlan(images, [c.M for c in cases], [c.sigma for c in cases], [c.iters for c in cases])
+        return p, p.pack_codebooks([c.w0 for c in cases])
+    good, w0 = plan_of(imgs)
+    bad_imgs = list(imgs)
+    bad_imgs[2] = imgs[2].clone()
+    u0, v0 = (int(round(x)) for x in cases[2].w0[0])  # under codevector 0: its first map read is NaN
+    bad_imgs[2][u0, v0] = float("nan")
+    bad, _ = plan_of(bad_imgs)
+    outs = []
+    for p in (good, bad):
+        n = p.n
+        w = torch.empty_like(w0)
+        d = torch.empty(n, dtype=torch.float64, device="cuda")
+        done = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        p.run(w0, w, d_out=d, iters_done=done, status=st)
+        torch.cuda.synchronize()
+        outs.append((w, d, done, st))
+    (wg, dg, doneg, stg), (wb, db, doneb, stb) = outs
+    assert torch.all(stg == 0) and torch.all(doneg == 100)
+    assert int(stb[2]) & gpu_lib.ITC_FIT_NONFINITE_SUMS and int(stb[2]) & gpu_lib.ITC_FIT_NONFINITE_D
+    assert int(doneb[2]) == 0 and not math.isfinite(float(db[2]))
+    assert torch.equal(bad.unpack(wb, 2), bad.unpack(w0, 2))
+    for i in (0, 1, 3, 4, 5):
+        assert int(stb[i]) == 0 and int(doneb[i]) == 100
+        assert torch.equal(bad.unpack(wb, i), good.unpack(wg, i)) and float(db[i]) == float(dg[i])
 
 
 def test_batched_theta_and_graph_replay(gpu_lib):
