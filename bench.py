@@ -188,6 +188,22 @@ def cpu_legs(cases, seconds):
     return cpu, ctx
 
 
+def capture(fn, dev="cuda"):
+    """fn captured in a HIP graph, after one warm-up call on a side stream."""
+    import torch
+
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
 def gpu_extras(dev, cases, itc, synth):
     """Secondary measurements: device copy and fill rates, the convolution per
     sigma class of the silhouette batch, the single-image workloads (512^2 and
@@ -245,34 +261,32 @@ def gpu_extras(dev, cases, itc, synth):
         wout = torch.empty_like(w0)
         dtr = torch.empty(c.iters + 1, dtype=torch.float64, device=dev)
         dn = torch.empty(1, dtype=torch.int32, device=dev)
+        work = torch.empty(itc.fit_wide_work_bytes(c.M), dtype=torch.uint8, device=dev)
 
         def conv():
             itc.precompute(img, c.sigma, scale=c.scale, out=maps)
 
-        def run():
+        def run_one():   # Algorithm 1's loop in one workgroup
             conv()
             itc._check(lib.itc_lattice_fit(itc.ctypes.byref(maps.desc), itc._ptr(maps.buf), itc._ptr(maps.s_x),
                                            c.M, itc._ptr(w0), c.iters, -1.0, itc._ptr(wout), itc._ptr(dtr),
                                            itc._ptr(dn), itc._stream()))
 
-        graphs = []
-        for fn in (conv, run):
-            s = torch.cuda.Stream(device=dev)
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                fn()
-            torch.cuda.current_stream().wait_stream(s)
-            torch.cuda.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                fn()
-            graphs.append(g)
-        t_conv = timed(graphs[0].replay)
-        t_run = timed(graphs[1].replay)
+        def run_wide():  # one launch per sweep over M / 32 workgroups
+            conv()
+            itc._check(lib.itc_lattice_fit_wide(itc.ctypes.byref(maps.desc), itc._ptr(maps.buf),
+                                                itc._ptr(maps.s_x), c.M, itc._ptr(w0), c.iters, -1.0,
+                                                itc._ptr(wout), itc._ptr(dtr), itc._ptr(dn), itc._ptr(work),
+                                                work.numel(), itc._stream()))
+
+        t_conv, t_one, t_wide = (timed(capture(fn).replay) for fn in (conv, run_one, run_wide))
         singles.append({"workload": c.name, "H": int(c.img.shape[0]), "W": int(c.img.shape[1]), "M": c.M,
-                        "sigma": c.sigma, "sweeps": c.iters, "images_per_s": 1.0 / t_run, "ms": t_run * 1e3,
-                        "conv_ms": t_conv * 1e3, "conv_gbs": 13.0 * c.img.size / t_conv / 1e9})
-        del maps, graphs
+                        "sigma": c.sigma, "sweeps": c.iters, "conv_ms": t_conv * 1e3,
+                        "conv_gbs": 13.0 * c.img.size / t_conv / 1e9,
+                        "one_workgroup": {"ms": t_one * 1e3, "images_per_s": 1.0 / t_one},
+                        "wide": {"ms": t_wide * 1e3, "images_per_s": 1.0 / t_wide,
+                                 "us_per_sweep": (t_wide - t_conv) / (c.iters + 2) * 1e6}})
+        del maps
     out["single_image"] = singles
 
     # Section 5 weighting: chamfer transform of every silhouette, then the
@@ -485,18 +499,6 @@ def main():
     # fit another; each is captured in a graph of its own, and HIP events
     # recorded between the replays (on the replay stream) time every launch of
     # the timed steps.
-    def capture(fn):
-        side = torch.cuda.Stream(device=dev)
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            fn()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            fn()
-        return g
-
     conv_fn = plan.precompute
     fit_fn = lambda: plan.fit(w0, w, sx, dd, done)  # noqa: E731
     if args.eager:

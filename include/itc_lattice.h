@@ -145,6 +145,31 @@ itc_status itc_lattice_fit(const itc_lattice_desc* d, const void* maps, const do
                            double* d_trace, int32_t* iters_done, void* stream);
 
 /*
+ * Algorithm 1's loop as itc_lattice_fit computes it (same arguments and
+ * outputs, same sweeps, theta stop and D trace), spread over several
+ * workgroups for one large image: one launch per sweep, each of which first
+ * reduces the previous sweep's per-workgroup FP64 partials of S_XW and S_W in
+ * workgroup order, so results are reproducible run to run (they differ from
+ * itc_lattice_fit's by the summation order of the codebook terms). All
+ * iters + 2 launches are enqueued at once; launches after the stop return at
+ * once, so the call is safe to capture in a HIP graph.
+ *   work        device, itc_lattice_fit_wide_work_bytes(M) bytes, 256-byte
+ *               aligned, owned by the caller; its contents on entry do not
+ *               matter and are unspecified on return. Calls that overlap on
+ *               one work buffer race.
+ *   work_bytes  its size; smaller than required: ITC_E_ARG.
+ * FP32 maps only (real_dtype ITC_F32, else ITC_E_UNSUPPORTED).
+ */
+itc_status itc_lattice_fit_wide(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
+                                const float* w_init, int32_t iters, double theta, float* w_out,
+                                double* d_trace, int32_t* iters_done, void* work, size_t work_bytes,
+                                void* stream);
+
+/* Work buffer bytes itc_lattice_fit_wide needs for M codevectors; 0 if M is
+ * outside 1..ITC_MAX_CODEVECTORS. */
+size_t itc_lattice_fit_wide_work_bytes(int32_t M);
+
+/*
  * Eq. (1) for codebook `w` ([M][2], real type): D = log S_W + log S_X -
  * 2 log S_XW, written to `d_out` (one double).
  */

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libitc_lattice.so")
 
-SOURCES = ["conv.hip", "conv_mfma.hip", "fit.hip", "adjoint.hip", "chamfer.hip", "literal.hip", "labels.hip", "recursive.hip", "volume.hip", "itc_lattice.cpp"]
+SOURCES = ["conv.hip", "conv_mfma.hip", "fit.hip", "fit_wide.hip", "adjoint.hip", "chamfer.hip", "literal.hip", "labels.hip", "recursive.hip", "volume.hip", "itc_lattice.cpp"]
 ARCH = "gfx950"
 
 

@@ -228,6 +228,16 @@ int fit_passes_of(int M);
 hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
                       int grid, hipStream_t s, const ImageDesc* h_image);
 
+// The fit of one FP32 image over several workgroups, one launch per sweep:
+// workgroups used, work buffer bytes (256-byte multiple) and shared memory
+// bytes for M codevectors.
+int fit_wide_groups(int M);
+size_t fit_wide_work_bytes(int M);
+size_t fit_wide_smem(int M);
+hipError_t launch_fit_wide(const ImageDesc& im, const void* maps, const double* s_x, const float* w_init, int iters,
+                           double theta, float* w_out, double* d_trace, int32_t* iters_done, void* work,
+                           hipStream_t s);
+
 // dL/dh over one 64 x 64 pixel tile of an image.
 struct GradTile {
   int32_t img;

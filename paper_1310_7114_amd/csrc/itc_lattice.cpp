@@ -434,6 +434,37 @@ itc_status itc_lattice_fit(const itc_lattice_desc* d, const void* maps, const do
   return fit_common(d, maps, s_x, M, w_init, iters, theta, w_out, d_trace, nullptr, iters_done, true, stream);
 }
 
+size_t itc_lattice_fit_wide_work_bytes(int32_t M) {
+  if (M < 1 || M > ITC_MAX_CODEVECTORS) return 0;
+  return itc::fit_wide_work_bytes(M);
+}
+
+itc_status itc_lattice_fit_wide(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
+                                const float* w_init, int32_t iters, double theta, float* w_out, double* d_trace,
+                                int32_t* iters_done, void* work, size_t work_bytes, void* stream) {
+  TraceRange trace_range("itc_lattice_fit_wide");
+  int R = 0, rc = 0;
+  itc_status st = check_desc(d, &R, &rc, false);
+  if (st != ITC_OK) return st;
+  if (d->real_dtype != ITC_F32) return fail(ITC_E_UNSUPPORTED, "the wide fit takes FP32 maps only");
+  if (!maps || !w_init || !w_out || !work) return fail(ITC_E_NULL, "maps, w_init, w_out and work must be non-NULL");
+  if (d_trace && !s_x) return fail(ITC_E_NULL, "s_x is required for the divergence");
+  if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
+  if (M > ITC_MAX_CODEVECTORS) return fail(ITC_E_UNSUPPORTED, "M %d exceeds %d", M, ITC_MAX_CODEVECTORS);
+  if (iters < 0) return fail(ITC_E_ARG, "iters must be >= 0 (got %d)", iters);
+  if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
+  if (!aligned256(maps) || !aligned256(work)) return fail(ITC_E_ARG, "maps and work must be 256-byte aligned");
+  if (work_bytes < itc::fit_wide_work_bytes(M))
+    return fail(ITC_E_ARG, "work buffer of %zu bytes, %zu needed", work_bytes, itc::fit_wide_work_bytes(M));
+  ImageDesc im = make_image(*d, R, rc);
+  im.M = M;
+  im.iters = iters;
+  hipError_t e = itc::launch_fit_wide(im, maps, s_x, w_init, iters, theta, w_out, d_trace, iters_done, work,
+                                      (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "wide fit launch");
+  return ok();
+}
+
 itc_status itc_lattice_divergence(const itc_lattice_desc* d, const void* maps, const double* s_x, int32_t M,
                                   const void* w, double* d_out, void* stream) {
   TraceRange trace_range("itc_lattice_divergence");

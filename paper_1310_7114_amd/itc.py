@@ -65,6 +65,9 @@ SIGNATURES = {
     "itc_lattice_precompute": (ctypes.c_int, [_DP, _P, _P, _P, _P]),
     "itc_lattice_fit": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                        _P, _P, _P, _P]),
+    "itc_lattice_fit_wide": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                            _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "itc_lattice_fit_wide_work_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "itc_lattice_divergence": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "itc_lattice_divergence_backward": (ctypes.c_int, [_DP, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "itc_lattice_plan_create": (ctypes.c_int, [ctypes.POINTER(Batch), ctypes.POINTER(ctypes.c_void_p)]),
@@ -220,6 +223,29 @@ def fit(maps: Maps, w_init: torch.Tensor, iters: int, theta: float = -1.0, trace
     done = torch.zeros(1, dtype=torch.int32, device=w_init.device)
     _check(load().itc_lattice_fit(ctypes.byref(maps.desc), _ptr(maps.buf), _ptr(maps.s_x), M, _ptr(w_init),
                                   int(iters), float(theta), _ptr(w_out), _ptr(d_trace), _ptr(done), _stream()))
+    return w_out, d_trace, done
+
+
+def fit_wide_work_bytes(M: int) -> int:
+    return int(load().itc_lattice_fit_wide_work_bytes(int(M)))
+
+
+def fit_wide(maps: Maps, w_init: torch.Tensor, iters: int, theta: float = -1.0, trace: bool = True,
+             w_out: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None):
+    """fit() over several workgroups, one launch per sweep (FP32 maps); `work`
+    (uint8, fit_wide_work_bytes(M) bytes) is allocated when not given.
+    Returns (W, D trace or None, iterations done tensor)."""
+    w_init = w_init.to(torch.float32).contiguous()
+    M = int(w_init.shape[0])
+    if w_out is None:
+        w_out = torch.empty_like(w_init)
+    if work is None:
+        work = torch.empty(fit_wide_work_bytes(M), dtype=torch.uint8, device=w_init.device)
+    d_trace = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=w_init.device) if trace else None
+    done = torch.zeros(1, dtype=torch.int32, device=w_init.device)
+    _check(load().itc_lattice_fit_wide(ctypes.byref(maps.desc), _ptr(maps.buf), _ptr(maps.s_x), M, _ptr(w_init),
+                                       int(iters), float(theta), _ptr(w_out), _ptr(d_trace), _ptr(done),
+                                       _ptr(work), int(work.numel()), _stream()))
     return w_out, d_trace, done
 
 

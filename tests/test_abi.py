@@ -109,6 +109,29 @@ def test_null_and_range_arguments(itc):
     assert lib.itc_lattice_plan_set_conv_shape(None, 0, 256, 0) == 1
 
 
+def test_fit_wide_arguments(itc):
+    import torch
+    lib = itc.load()
+    P = ctypes.c_void_p(256)
+    wb = lib.itc_lattice_fit_wide_work_bytes
+    assert wb(0) == 0 and wb(1025) == 0
+    n = wb(500)
+    assert n > 0 and n % 256 == 0 and n >= 500 * (2 * 16 + 2 * 32)   # positions and terms, double buffered
+    fw = lib.itc_lattice_fit_wide
+    d = itc.make_desc(16, 16, 2.0)
+    args = lambda **k: dict(dict(d=ctypes.byref(d), maps=P, s_x=P, M=4, w=P, iters=3, theta=-1.0, out=P,  # noqa: E731
+                                 trace=None, done=None, work=P, nb=wb(4), s=None), **k)
+    call = lambda a: fw(*a.values())  # noqa: E731
+    assert call(args(M=0)) == 2 and call(args(M=1025)) == 3 and call(args(iters=-1)) == 2
+    assert call(args(theta=float("nan"))) == 2
+    assert call(args(work=None)) == 1 and call(args(maps=None)) == 1
+    assert call(args(s_x=None, trace=P)) == 1                          # the trace needs s_x
+    assert call(args(nb=wb(4) - 1)) == 2                               # work buffer too small
+    assert call(args(work=ctypes.c_void_p(512 + 64))) == 2            # misaligned work
+    d64 = itc.make_desc(16, 16, 2.0, real_dtype=torch.float64)
+    assert call(args(d=ctypes.byref(d64))) == 3                        # FP32 maps only
+
+
 def test_chamfer_arguments(itc):
     lib = itc.load()
     P = ctypes.c_void_p(256)

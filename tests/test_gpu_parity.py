@@ -7,6 +7,8 @@ Tolerances:
          1e-4 px after one sweep from the same codebook, 1e-9 px (FP64)
   D      |D_gpu - D_ref| <= 1e-5 * max(1, |D|)
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -186,11 +188,17 @@ def test_fit_config2_full(gpu_lib):
     assert np.abs(tr - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
 
 
+@functools.lru_cache(maxsize=1)
+def config4_oracle():
+    case = S.config4_case()
+    return O.fit_lattice(case.weights, case.w0, case.sigma, case.R, case.iters)
+
+
 def test_fit_config4_full(gpu_lib):
     """2048 x 2048 gray weights g/255, M = 500, sigma = 6, 200 sweeps."""
     case = S.config4_case()
     m, w, tr, _ = run_fit(gpu_lib, case)
-    W_ref, tr_ref, _, maps_ref = O.fit_lattice(case.weights, case.w0, case.sigma, case.R, case.iters)
+    W_ref, tr_ref, _, maps_ref = config4_oracle()
     got = [p.cpu().double().numpy() for p in m.planes()]
     ref = (maps_ref[0],) + O.moment_maps(*maps_ref)
     for g, r in zip(got, ref):
@@ -266,3 +274,127 @@ def test_bitwise_reproducible(gpu_lib):
     pa = [p.cpu() for p in a[0].planes()]
     pb = [p.cpu() for p in b[0].planes()]
     assert all(torch.equal(x, y) for x, y in zip(pa, pb))
+
+
+# ----------------------------------------------------------------- wide fit
+# The single-image fit over several workgroups, one launch per sweep: the same
+# bars against the oracle as the single-workgroup fit.
+
+def run_fit_wide(itc, case, iters=None, theta=-1.0, w0=None, maps=None, work=None):
+    m = maps if maps is not None else itc.precompute(torch.from_numpy(case.img).to(DEV), case.sigma,
+                                                     scale=case.scale)
+    w0 = case.w0 if w0 is None else w0
+    w, tr, done = itc.fit_wide(m, torch.from_numpy(w0).to(DEV), case.iters if iters is None else iters,
+                               theta=theta, work=work)
+    torch.cuda.synchronize()
+    return m, w.cpu().double().numpy(), tr.cpu().numpy(), int(done.cpu()[0])
+
+
+def test_fit_wide_config4_full(gpu_lib):
+    """2048 x 2048, M = 500 (16 workgroups), sigma = 6, 200 sweeps."""
+    case = S.config4_case()
+    _, w, tr, done = run_fit_wide(gpu_lib, case)
+    W_ref, tr_ref, _, _ = config4_oracle()
+    assert done == case.iters
+    assert wdist(w, W_ref) <= 1e-3
+    assert np.abs(tr - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
+
+
+@pytest.mark.parametrize("seed", [1, 4])
+def test_fit_wide_config1(gpu_lib, seed):
+    case = S.config1_case(seed)
+    _, w, tr, done = run_fit_wide(gpu_lib, case)
+    W_ref, tr_ref, _, _ = O.fit_lattice(case.weights, case.w0, case.sigma, case.R, case.iters)
+    assert done == case.iters
+    assert wdist(w, W_ref) <= 1e-3
+    assert np.abs(tr - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
+
+
+def test_fit_wide_theta_stop(gpu_lib):
+    """theta = 0.15 on the 512 x 512 shapes: the oracle stops after sweep 28 with its largest step
+    1.6e-3 px below theta and every earlier one at least 3.9e-3 px above it."""
+    case = S.config2_case()
+    _, w, tr, done = run_fit_wide(gpu_lib, case, theta=0.15)
+    W_ref, tr_ref, done_ref, _ = O.fit_lattice(case.weights, case.w0, case.sigma, case.R, case.iters, theta=0.15)
+    assert done == done_ref == 28
+    assert wdist(w, W_ref) <= 1e-3
+    assert np.abs(tr[:done + 1] - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
+    assert np.all(np.isnan(tr[done + 1:]))   # entries past the stop are untouched
+
+
+@pytest.mark.parametrize("M", [1, 31, 33, 257])
+def test_fit_wide_ragged_codebooks(gpu_lib, M):
+    """Codebook sizes that leave the last workgroup partly empty (32 codevectors per workgroup),
+    two codevectors off the data (frozen) included when M allows."""
+    case = S.config2_case()
+    rng = np.random.default_rng(M)
+    on = np.argwhere(case.img > 0)
+    w0 = on[rng.choice(len(on), size=M, replace=False)].astype(np.float64) + 0.25
+    if M >= 16:
+        w0[-2:] = [[-40.0, 10.0], [600.0, 600.0]]
+    c = S.LatticeCase(case.img, case.scale, w0, case.sigma, case.R, 15)
+    _, w, tr, done = run_fit_wide(gpu_lib, c)
+    W_ref, tr_ref, _, _ = O.fit_lattice(case.weights, w0, case.sigma, case.R, 15)
+    assert done == 15
+    assert wdist(w, W_ref) <= 1e-3
+    if M >= 16:
+        assert np.array_equal(w[-2:], w0[-2:])
+    assert np.abs(tr - tr_ref).max() <= 1e-5 * max(1.0, abs(tr_ref).max())
+
+
+def test_fit_wide_zero_iterations_and_alias(gpu_lib):
+    case = S.config1_case(2)
+    m, w, tr, done = run_fit_wide(gpu_lib, case, iters=0)
+    assert done == 0 and np.array_equal(w, case.w0.astype(np.float32).astype(np.float64))
+    d = float(gpu_lib.divergence(m, torch.from_numpy(case.w0).to(DEV)).cpu()[0])
+    assert abs(tr[0] - d) <= 1e-6 * max(1.0, abs(d))
+    wi = torch.from_numpy(case.w0).to(DEV, torch.float32)
+    ref, _, _ = gpu_lib.fit_wide(m, wi.clone(), 10)
+    wa = wi.clone()
+    gpu_lib.fit_wide(m, wa, 10, w_out=wa)
+    torch.cuda.synchronize()
+    assert torch.equal(wa, ref)
+
+
+def test_fit_wide_reproducible_and_graph_replays(gpu_lib):
+    """Bitwise equal run to run (fixed-order partial sums), and from a captured graph replayed
+    three times with other work in between; a dirty work buffer does not matter."""
+    case = S.config2_case()
+    m = gpu_lib.precompute(torch.from_numpy(case.img).to(DEV), case.sigma)
+    w0 = torch.from_numpy(case.w0).to(DEV, torch.float32)
+    work = torch.full((gpu_lib.fit_wide_work_bytes(case.M),), 0x7f, dtype=torch.uint8, device=DEV)
+    a = gpu_lib.fit_wide(m, w0, 30, work=work)
+    b = gpu_lib.fit_wide(m, w0, 30, work=work)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and int(a[2]) == int(b[2]) == 30
+    w_out = torch.empty_like(w0)
+    side = torch.cuda.Stream(device=DEV)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gpu_lib.fit_wide(m, w0, 30, w_out=w_out, work=work, trace=False)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpu_lib.fit_wide(m, w0, 30, w_out=w_out, work=work, trace=False)
+    for _ in range(3):
+        w_out.fill_(float("nan"))
+        work.fill_(0x55)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(w_out, a[0])
+
+
+def test_fit_wide_nonfinite_weights_stop(gpu_lib):
+    """A NaN weight makes S_XW non-finite at the first codebook: both fits stop there."""
+    case = S.config1_case(3)
+    x = torch.from_numpy(case.img.astype(np.float32)).to(DEV)
+    i, j = np.floor(case.w0[0]).astype(int)
+    x[i, j] = float("nan")   # a corner of codevector 0's cell
+    m = gpu_lib.precompute(x, case.sigma)
+    w0 = torch.from_numpy(case.w0).to(DEV, torch.float32)
+    w, _, done = gpu_lib.fit_wide(m, w0, 20)
+    w1, _, done1 = gpu_lib.fit(m, w0, 20)
+    torch.cuda.synchronize()
+    assert int(done) == int(done1) == 0
+    assert torch.equal(w, w0) and torch.equal(w1, w0)
