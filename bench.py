@@ -343,6 +343,21 @@ def gpu_extras(dev, cases, itc, synth):
                                 "graph_ms_total": g20 * 1e3, "graph_ms_per_sweep": (g20 - g0) / 20 * 1e3}
     del work, graphs
 
+    # Algorithm 1 with the paper's widths where xi exceeds the masks: P by
+    # recursive filtering once, then the sweeps (silhouette 49 of the batch)
+    c49 = synth.config3_cases(indices=[49])[0]
+    xi49, om49 = paper_widths(float(c49.img.sum()), c49.M)
+    x49 = torch.from_numpy(c49.img).to(dev)
+    w049 = torch.from_numpy(c49.w0).to(dev).to(torch.int32)
+    m49 = itc.precompute_recursive(x49, xi49)
+    t_p = timed(lambda: itc.precompute_recursive(x49, xi49))
+    g_lit = {k: capture(lambda k=k: itc.fit_literal_density(m49, w049, om49, k, trace=False)) for k in (20, 0)}
+    t20, t0 = timed(g_lit[20].replay, reps=5), timed(g_lit[0].replay, reps=5)
+    out["literal_recursive_silhouette"] = {"index": 49, "H": int(c49.img.shape[0]), "W": int(c49.img.shape[1]),
+                                           "M": c49.M, "xi": xi49, "omega": om49, "p_ms": t_p * 1e3,
+                                           "ms_per_sweep": (t20 - t0) / 20 * 1e3}
+    del m49, g_lit
+
     # maps by recursive filtering: cost per pixel independent of sigma
     c4 = synth.config4_case(0)
     x4 = torch.from_numpy(c4.img).to(dev)

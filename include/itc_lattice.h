@@ -268,6 +268,25 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
                                    void* work, void* stream);
 
 /*
+ * Algorithm 1 as itc_lattice_literal_fit, from a density P the caller has
+ * computed once: plane A of `maps`, as itc_lattice_precompute or
+ * itc_lattice_precompute_recursive wrote it for `d`. The recursive maps give P
+ * for any width xi = d->sigma >= 0.5 (Section 3.1: recursive filters replace
+ * the masks at large widths), so the paper's widths omega = sqrt(N/M)/2,
+ * xi = omega/2 run on any image; the weights are not read. `work` at
+ * itc_lattice_literal_density_work_bytes(d, M, omega, radius_omega) bytes,
+ * device, 256-byte aligned (overwritten); `maps` 256-byte aligned (read).
+ * Other arguments, outputs and errors as itc_lattice_literal_fit; d->radius
+ * and the radius limit of the masks do not apply.
+ */
+size_t itc_lattice_literal_density_work_bytes(const itc_lattice_desc* d, int32_t M, double omega,
+                                              int32_t radius_omega);
+itc_status itc_lattice_literal_fit_density(const itc_lattice_desc* d, const void* maps, double omega,
+                                           int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                           double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,
+                                           void* work, void* stream);
+
+/*
  * Segments of a codebook (the shape segments of Section 4): labels(x) is the
  * index of the codevector nearest to pixel x (Euclidean; the smaller index on
  * equal distances) for every pixel of weight h(x) = weight_scale * stored > 0,

@@ -11,4 +11,4 @@ from .volume import (volume_maps, read_trilinear, volume_codebook_terms, volume_
                      volume_divergence, fit_volume)
 from .recursive import yvv_coefficients, yvv_filter_1d, recursive_density, recursive_maps  # noqa: F401
 from .literal import (paper_widths, literal_q, literal_terms, literal_step, literal_divergence,  # noqa: F401
-                      fit_literal)
+                      fit_literal, fit_literal_density)

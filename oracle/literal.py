@@ -32,7 +32,8 @@ import numpy as np
 
 from .itc_oracle import density_map, taps
 
-__all__ = ["paper_widths", "literal_q", "literal_terms", "literal_step", "literal_divergence", "fit_literal"]
+__all__ = ["paper_widths", "literal_q", "literal_terms", "literal_step", "literal_divergence", "fit_literal",
+           "fit_literal_density"]
 
 
 def paper_widths(N: float, M: int):
@@ -125,8 +126,15 @@ def fit_literal(I, W0, xi, omega, iters, R_xi=None, R_omega=None, theta=None):
     W0 must hold lattice points. Stops early when max_k ||w_k^new - w_k|| <= theta."""
     I = np.asarray(I, np.float64)
     R_xi = int(math.ceil(3.0 * xi - 1e-12)) if R_xi is None else int(R_xi)
-    R_om = int(math.ceil(3.0 * omega - 1e-12)) if R_omega is None else int(R_omega)
     P = density_map(I, xi, R_xi)
+    return fit_literal_density(P, W0, omega, iters, R_omega, theta)
+
+
+def fit_literal_density(P, W0, omega, iters, R_omega=None, theta=None):
+    """Algorithm 1's loop from a given density P (computed once, by the masks or by the recursive
+    filter of Section 3.1): returns (lattice codebook, D trace over W_0..W_T, sweeps done, P)."""
+    P = np.asarray(P, np.float64)
+    R_om = int(math.ceil(3.0 * omega - 1e-12)) if R_omega is None else int(R_omega)
     v_x = float(np.sum(P * P))
     Wc = np.array(W0, dtype=np.float64)
     if not np.array_equal(Wc, np.floor(Wc)):
@@ -135,7 +143,7 @@ def fit_literal(I, W0, xi, omega, iters, R_xi=None, R_omega=None, theta=None):
     done = 0
     for _ in range(iters):
         wn, _, _, _ = literal_step(P, Wc, omega, R_om)
-        wn = _to_lattice(wn, I.shape)
+        wn = _to_lattice(wn, P.shape)
         step = float(np.max(np.linalg.norm(wn - Wc, axis=1)))
         Wc = wn
         done += 1

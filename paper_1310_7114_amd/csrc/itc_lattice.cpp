@@ -769,14 +769,15 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
   return ok();
 }
 
-// Algorithm 1: the work buffer holds the maps of P, then the taps and window
-// overlaps, the V(X) row-block sums, the per-codevector sums and the state.
+// Algorithm 1: the work buffer holds the maps of P (unless the caller gives
+// P), then the taps and window overlaps, the V(X) row-block sums, the
+// per-codevector sums and the state.
 struct LiteralLayout {
   size_t maps, taps, vx, terms, state, total;
   int R, nvx;
 };
 
-static bool literal_layout(const itc_lattice_desc& d, int32_t M, double omega, int32_t radius_omega,
+static bool literal_layout(const itc_lattice_desc& d, int32_t M, double omega, int32_t radius_omega, bool with_maps,
                            LiteralLayout& L) {
   if (!(omega > 0.0) || !std::isfinite(omega)) return false;
   const double rr = std::ceil(3.0 * omega - 1e-12);
@@ -785,7 +786,7 @@ static bool literal_layout(const itc_lattice_desc& d, int32_t M, double omega, i
   L.R = R;
   L.nvx = (d.height + 15) / 16;
   L.maps = 0;
-  L.taps = (maps_bytes_of(d) + 255) / 256 * 256;
+  L.taps = with_maps ? (maps_bytes_of(d) + 255) / 256 * 256 : 0;
   L.vx = L.taps + (size_t)(3 * R + 2) * sizeof(double);
   L.terms = L.vx + (size_t)L.nvx * sizeof(double);
   L.state = L.terms + (size_t)6 * M * sizeof(double);
@@ -797,24 +798,35 @@ size_t itc_lattice_literal_work_bytes(const itc_lattice_desc* d, int32_t M, doub
   int R = 0, rc = 0;
   if (!d || check_desc(d, &R, &rc) != ITC_OK) return 0;
   LiteralLayout L;
-  if (!literal_layout(*d, M, omega, radius_omega, L)) return 0;
+  if (!literal_layout(*d, M, omega, radius_omega, true, L)) return 0;
+  return L.total;
+}
+
+size_t itc_lattice_literal_density_work_bytes(const itc_lattice_desc* d, int32_t M, double omega,
+                                              int32_t radius_omega) {
+  int R = 0, rc = 0;
+  if (!d || check_desc(d, &R, &rc, false) != ITC_OK) return 0;
+  LiteralLayout L;
+  if (!literal_layout(*d, M, omega, radius_omega, false, L)) return 0;
   return L.total;
 }
 
 }  // extern "C"
 
-// Algorithm 1 with a work buffer of `work_cap` bytes (the caller's, of the
-// size itc_lattice_literal_work_bytes gives, or the library's static
-// scratch); ITC_E_UNSUPPORTED when the problem needs more.
-itc_status itc::literal_fit_with_work(const itc_lattice_desc* d, const void* weights, double omega,
-                                      int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
-                                      double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
-                                      size_t work_cap, void* stream) {
-  TraceRange trace_range("itc_lattice_literal_fit");
+// Algorithm 1 with P from the weights (density == NULL: the masks of width
+// xi = d->sigma, written into the work buffer) or from the caller's maps
+// (plane A of `density`), and a work buffer of `work_cap` bytes (the
+// caller's, or the library's static scratch); ITC_E_UNSUPPORTED when the
+// problem needs more.
+static itc_status literal_fit_impl(const itc_lattice_desc* d, const void* weights, const void* density, double omega,
+                                   int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters, double theta,
+                                   int32_t* w_out, double* d_trace, int32_t* iters_done, void* work, size_t work_cap,
+                                   void* stream) {
   int R = 0, rc = 0;
-  itc_status st = check_desc(d, &R, &rc);
+  itc_status st = check_desc(d, &R, &rc, density == nullptr);
   if (st != ITC_OK) return st;
-  if (!weights || !w_init || !w_out || !work) return fail(ITC_E_NULL, "weights, w_init, w_out and work must be non-NULL");
+  if (!(weights || density) || !w_init || !w_out || !work)
+    return fail(ITC_E_NULL, "the weights (or the density maps), w_init, w_out and work must be non-NULL");
   if (d->real_dtype != ITC_F32) return fail(ITC_E_UNSUPPORTED, "Algorithm 1 runs with real_dtype ITC_F32");
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ITC_E_ARG, "omega must be finite and > 0 (got %g)", omega);
   if (M < 1) return fail(ITC_E_ARG, "M must be >= 1 (got %d)", M);
@@ -822,21 +834,24 @@ itc_status itc::literal_fit_with_work(const itc_lattice_desc* d, const void* wei
   if (iters < 0) return fail(ITC_E_ARG, "iters must be >= 0 (got %d)", iters);
   if (std::isnan(theta)) return fail(ITC_E_ARG, "theta is NaN");
   if (!aligned256(work)) return fail(ITC_E_ARG, "work must be 256-byte aligned");
+  if (density && !aligned256(density)) return fail(ITC_E_ARG, "the density maps must be 256-byte aligned");
   LiteralLayout L;
-  if (!literal_layout(*d, M, omega, radius_omega, L))
+  if (!literal_layout(*d, M, omega, radius_omega, density == nullptr, L))
     return fail(radius_omega < 0 ? ITC_E_ARG : ITC_E_UNSUPPORTED, "omega window radius must be 1..%d",
                 ITC_MAX_LITERAL_RADIUS);
   if (L.total > work_cap)
     return fail(ITC_E_UNSUPPORTED, "the problem needs %zu bytes of work memory, more than the %zu available",
                 L.total, work_cap);
-  ImageDesc im = make_image(*d, R, rc);
   hipStream_t s = (hipStream_t)stream;
   char* wb = (char*)work;
-  hipError_t e = itc::launch_conv_image(false, im, weights, wb + L.maps, s);
-  if (e != hipSuccess) return device_fail(e, "convolution launch");
+  if (!density) {
+    const ImageDesc im = make_image(*d, R, rc);
+    hipError_t e = itc::launch_conv_image(false, im, weights, wb + L.maps, s);
+    if (e != hipSuccess) return device_fail(e, "convolution launch");
+  }
   itc::LiteralArgs la;
   std::memset(&la, 0, sizeof la);
-  la.P = reinterpret_cast<const float*>(wb + L.maps);
+  la.P = reinterpret_cast<const float*>(density ? density : wb + L.maps);
   la.H = d->height;
   la.W = d->width;
   la.M = M;
@@ -851,9 +866,19 @@ itc_status itc::literal_fit_with_work(const itc_lattice_desc* d, const void* wei
   la.state = reinterpret_cast<int32_t*>(wb + L.state);
   la.d_trace = d_trace;
   la.iters_done = iters_done;
-  e = itc::launch_literal(la, w_init, w_out, s);
+  hipError_t e = itc::launch_literal(la, w_init, w_out, s);
   if (e != hipSuccess) return device_fail(e, "Algorithm 1 launch");
   return ok();
+}
+
+itc_status itc::literal_fit_with_work(const itc_lattice_desc* d, const void* weights, double omega,
+                                      int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                      double theta, int32_t* w_out, double* d_trace, int32_t* iters_done, void* work,
+                                      size_t work_cap, void* stream) {
+  TraceRange trace_range("itc_lattice_literal_fit");
+  if (!weights) return fail(ITC_E_NULL, "weights must be non-NULL");
+  return literal_fit_impl(d, weights, nullptr, omega, radius_omega, M, w_init, iters, theta, w_out, d_trace,
+                          iters_done, work, work_cap, stream);
 }
 
 itc_status itc::report_error(itc_status s, const char* msg) { return fail(s, "%s", msg); }
@@ -866,6 +891,16 @@ itc_status itc_lattice_literal_fit(const itc_lattice_desc* d, const void* weight
                                    void* stream) {
   return itc::literal_fit_with_work(d, weights, omega, radius_omega, M, w_init, iters, theta, w_out, d_trace,
                                     iters_done, work, SIZE_MAX, stream);
+}
+
+itc_status itc_lattice_literal_fit_density(const itc_lattice_desc* d, const void* maps, double omega,
+                                           int32_t radius_omega, int32_t M, const int32_t* w_init, int32_t iters,
+                                           double theta, int32_t* w_out, double* d_trace, int32_t* iters_done,
+                                           void* work, void* stream) {
+  TraceRange trace_range("itc_lattice_literal_fit_density");
+  if (!maps) return fail(ITC_E_NULL, "maps must be non-NULL");
+  return literal_fit_impl(d, nullptr, maps, omega, radius_omega, M, w_init, iters, theta, w_out, d_trace,
+                          iters_done, work, SIZE_MAX, stream);
 }
 
 itc_status itc_lattice_label(const itc_lattice_desc* d, const void* weights, int32_t M, const void* w,

@@ -91,6 +91,10 @@ SIGNATURES = {
                                                ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_literal_fit_noalloc": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                                        _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P]),
+    "itc_lattice_literal_density_work_bytes": (ctypes.c_size_t, [_DP, ctypes.c_int32, ctypes.c_double,
+                                                                 ctypes.c_int32]),
+    "itc_lattice_literal_fit_density": (ctypes.c_int, [_DP, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                                       _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
     "itc_lattice_chamfer_batched": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "itc_lattice_plan_size": (ctypes.c_int32, [_P]),
     "itc_lattice_plan_conv_classes": (ctypes.c_int32, [_P]),
@@ -396,6 +400,28 @@ def fit_literal(weights: torch.Tensor, w_init: torch.Tensor, xi: float, omega: f
     _check(load().itc_lattice_literal_fit(ctypes.byref(desc), _ptr(weights), float(omega), int(radius_omega), M,
                                           _ptr(w_init), int(iters), float(theta), _ptr(w_out), _ptr(d_trace),
                                           _ptr(done), _ptr(work), _stream()))
+    return w_out, d_trace, done
+
+
+def fit_literal_density(maps: Maps, w_init: torch.Tensor, omega: float, iters: int, theta: float = -1.0,
+                        radius_omega: int = 0, trace: bool = True, work: Optional[torch.Tensor] = None):
+    """Algorithm 1 from the density P = plane A of `maps` (precompute or precompute_recursive, any
+    width). w_init: (M, 2) int32 lattice points. Returns (W int32 (M, 2), D trace or None, sweeps done)."""
+    if maps.real_dtype != torch.float32:
+        raise ValueError("Algorithm 1 runs on FP32 maps")
+    w_init = w_init.to(torch.int32).contiguous()
+    M = int(w_init.shape[0])
+    nb = load().itc_lattice_literal_density_work_bytes(ctypes.byref(maps.desc), M, float(omega), int(radius_omega))
+    if nb == 0:
+        raise ItcError(2, "invalid Algorithm 1 parameters: " + load().itc_last_error().decode())
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=w_init.device)
+    w_out = torch.empty_like(w_init)
+    d_trace = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=w_init.device) if trace else None
+    done = torch.zeros(1, dtype=torch.int32, device=w_init.device)
+    _check(load().itc_lattice_literal_fit_density(ctypes.byref(maps.desc), _ptr(maps.buf), float(omega),
+                                                  int(radius_omega), M, _ptr(w_init), int(iters), float(theta),
+                                                  _ptr(w_out), _ptr(d_trace), _ptr(done), _ptr(work), _stream()))
     return w_out, d_trace, done
 
 

@@ -132,6 +132,25 @@ def test_fit_wide_arguments(itc):
     assert call(args(d=ctypes.byref(d64))) == 3                        # FP32 maps only
 
 
+def test_literal_density_arguments(itc):
+    lib = itc.load()
+    P = ctypes.c_void_p(256)
+    d = itc.make_desc(300, 360, 28.0, radius=1)   # recursive maps: any width
+    wb = lib.itc_lattice_literal_density_work_bytes
+    n = wb(ctypes.byref(d), 4, 56.0, 0)
+    assert n > 0 and n % 256 == 0 and n < lib.itc_lattice_literal_work_bytes(ctypes.byref(itc.make_desc(300, 360, 5.0)), 4, 56.0, 0)
+    assert wb(ctypes.byref(d), 4, 90.0, 0) == 0       # ceil(3 omega) beyond ITC_MAX_LITERAL_RADIUS
+    assert wb(ctypes.byref(d), 0, 56.0, 0) == 0
+    fd = lib.itc_lattice_literal_fit_density
+    assert fd(ctypes.byref(d), None, 56.0, 0, 4, P, 5, -1.0, P, None, None, P, None) == 1   # maps NULL
+    assert fd(ctypes.byref(d), P, 56.0, 0, 4, P, 5, -1.0, P, None, None, None, None) == 1   # work NULL
+    assert fd(ctypes.byref(d), ctypes.c_void_p(512 + 4), 56.0, 0, 4, P, 5, -1.0, P, None, None, P, None) == 2
+    assert fd(ctypes.byref(d), P, 0.0, 0, 4, P, 5, -1.0, P, None, None, P, None) == 2      # omega
+    assert fd(ctypes.byref(d), P, 90.0, 0, 4, P, 5, -1.0, P, None, None, P, None) == 3     # window too wide
+    d64 = itc.make_desc(300, 360, 28.0, real_dtype=__import__("torch").float64, radius=1)
+    assert fd(ctypes.byref(d64), P, 56.0, 0, 4, P, 5, -1.0, P, None, None, P, None) == 3
+
+
 def test_chamfer_arguments(itc):
     lib = itc.load()
     P = ctypes.c_void_p(256)

@@ -62,20 +62,24 @@ def oracle_step(P, W, omega, Ro, shape):
     return wn, r
 
 
-def check_gpu_trajectory(itc, case, xi, omega, T, theta=-1.0):
+def check_gpu_trajectory(itc, case, xi, omega, T, theta=-1.0, P=None, run=None):
     """Runs 1..T sweeps on the GPU and validates each against an oracle sweep from the GPU's previous
-    codebook. Returns (GPU codebooks, sweeps during which the GPU equals the oracle's own run, sweeps done)."""
-    Rx = int(math.ceil(3 * xi - 1e-12))
+    codebook. Returns (GPU codebooks, sweeps during which the GPU equals the oracle's own run, sweeps done).
+    P: the oracle's density (default: the masks of width xi); run(t, theta): the GPU call (default:
+    itc.fit_literal on the case's weights)."""
     Ro = int(math.ceil(3 * omega - 1e-12))
-    P = O.density_map(case.weights, xi, Rx)
+    if P is None:
+        P = O.density_map(case.weights, xi, int(math.ceil(3 * xi - 1e-12)))
+    if run is None:
+        run = lambda t, th: gpu_run(itc, case, xi, omega, t, theta=th)  # noqa: E731
     shape = case.img.shape
-    w_full, trace, done_full = gpu_run(itc, case, xi, omega, T, theta=theta)
+    w_full, trace, done_full = run(T, theta)
     prev = np.array(case.w0, np.float64)
     own = prev.copy()  # the oracle's own trajectory
     agreed, same = 0, True
     Ws = [prev]
     for t in range(1, done_full + 1):
-        w, _, done = gpu_run(itc, case, xi, omega, t)
+        w, _, done = run(t, -1.0)
         assert done == t
         raw, ref = oracle_step(P, prev, omega, Ro, shape)
         for k, ax in np.argwhere(w != ref):
@@ -152,3 +156,58 @@ def test_literal_rejects_bad_arguments(gpu_lib):
     for om, r in ((0.0, 0), (float("nan"), 0), (100.0, 0), (2.0, 257)):
         with pytest.raises(gpu_lib.ItcError):
             gpu_lib.fit_literal(x, w0, 1.0, om, 3, radius_omega=r)
+
+
+# ---------------------------------------------------- P by recursive filtering
+# The paper's widths on silhouettes whose xi exceeds the largest mask radius
+# (xi > 32 / 3 px): P from the recursive Gaussian (Section 3.1), computed once
+# on the GPU and handed to Algorithm 1; the oracle runs the same loop on its own
+# FP64 recursive density.
+
+def density_runner(itc, case, maps, omega):
+    w0 = torch.from_numpy(np.asarray(case.w0)).cuda().to(torch.int32)
+
+    def run(t, theta):
+        w, tr, done = itc.fit_literal_density(maps, w0, omega, t, theta=theta)
+        torch.cuda.synchronize()
+        return w.cpu().numpy().astype(np.float64), tr.cpu().numpy(), int(done.cpu()[0])
+    return run
+
+
+@pytest.mark.parametrize("index", [14, 49])
+def test_literal_recursive_density_paper_widths(gpu_lib, index):
+    """Silhouettes 14 (M = 64, xi = 11.1, omega = 22.3) and 49 (M = 17, xi = 15.6, omega = 31.2) of the
+    batch, with the paper's widths: beyond the masks, so P is the recursive density."""
+    import oracle.recursive as OR
+    case = S.config3_cases(indices=[index])[0]
+    xi, om = O.paper_widths(float(case.img.sum()), case.M)
+    assert xi > 32 / 3
+    maps = gpu_lib.precompute_recursive(torch.from_numpy(case.img).cuda(), xi, scale=case.scale)
+    P = OR.recursive_maps(case.weights, xi)[0]
+    _, agreed, done = check_gpu_trajectory(gpu_lib, case, xi, om, 8, P=P,
+                                           run=density_runner(gpu_lib, case, maps, om))
+    assert done == 8 and agreed >= 4
+
+
+def test_literal_recursive_density_wide_ellipse(gpu_lib):
+    """One large ellipse (about 50,000 pixels), M = 4: xi = 28, omega = 56 (windows of 337 x 337), and
+    the theta stop on a converged lattice codebook."""
+    import oracle.recursive as OR
+    m = np.zeros((300, 360), bool)
+    S.fill_ellipse(m, 150.0, 175.0, 95.0, 160.0, 0.4)
+    img = m.astype(np.uint8)
+    rng = np.random.default_rng(7)
+    on = np.argwhere(img > 0)
+    w0 = on[rng.choice(len(on), size=4, replace=False)].astype(np.float64)
+    case = S.LatticeCase(img, 1.0, w0, 1.0, 3, 40)
+    xi, om = O.paper_widths(float(img.sum()), 4)
+    assert 25 < xi < 35
+    maps = gpu_lib.precompute_recursive(torch.from_numpy(img).cuda(), xi)
+    P = OR.recursive_maps(img.astype(np.float64), xi)[0]
+    Ws, agreed, done = check_gpu_trajectory(gpu_lib, case, xi, om, 40, theta=0.5, P=P,
+                                            run=density_runner(gpu_lib, case, maps, om))
+    assert done < 40 and np.array_equal(Ws[-1], Ws[-2])  # stopped on a sweep that moved nothing
+    # the oracle's own run, where the two never parted, stops at the same sweep with the same codebook
+    Wo, _, doneo, _ = O.fit_literal_density(P, w0, om, 40, theta=0.5)
+    if agreed == done:
+        assert doneo == done and np.array_equal(Wo, Ws[-1])
