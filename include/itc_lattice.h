@@ -69,6 +69,7 @@ typedef enum { ITC_U8 = 0, ITC_F32 = 1, ITC_F64 = 2 } itc_dtype;
 #define ITC_MAX_RADIUS_F64 24
 #define ITC_MAX_CODEVECTORS 1024
 #define ITC_MAX_CHAMFER_WIDTH 16384 /* widest image the chamfer transform accepts */
+#define ITC_MAX_CHAMFER_HEIGHT 65535 /* tallest (column distances are kept as 16-bit integers) */
 #define ITC_MAX_CHAMFER_STEP 64     /* largest orthogonal step cost of the chamfer mask */
 #define ITC_MAX_LITERAL_RADIUS 256  /* largest window radius of G_omega in Algorithm 1 */
 
@@ -208,8 +209,10 @@ itc_status itc_lattice_divergence_backward(const itc_lattice_desc* d, const void
  *            left untouched), exact integer chamfer costs. It can be passed
  *            as an ITC_F32 weight image with the same pitch and
  *            weight_scale = 1/a.
- * Requires 1 <= a <= b <= 2a, a <= ITC_MAX_CHAMFER_STEP and
- * width <= ITC_MAX_CHAMFER_WIDTH. Asynchronous on `stream`; no allocation.
+ * Requires 1 <= a <= b <= 2a, a <= ITC_MAX_CHAMFER_STEP,
+ * width <= ITC_MAX_CHAMFER_WIDTH and height <= ITC_MAX_CHAMFER_HEIGHT.
+ * t_out is also the intermediate of the two passes. Asynchronous on
+ * `stream`; no allocation.
  */
 itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t a, int32_t b,
                                float* t_out, void* stream);

@@ -17,12 +17,18 @@
 //   g(i, l) = rows from (i, l) to the nearest background pixel of column l
 //   (rows -1 and H and columns -1 and W are background).
 //
-// Pass 1 (columns): one thread per column walks down and up the column and
-// writes g (columns of up to 1,024 rows are first packed into a bit mask, so
-// the image is read once and g written once). Pass 2 (rows): a workgroup stages one row of g in LDS and every
-// thread searches outward from its column, stopping once a |j - l| reaches
-// the best cost found (phi >= a |j - l|). Values are exact integers, stored
-// as FP32 so that T can feed the convolution as a weight image.
+// Pass 1 (columns): a workgroup of four waves takes a strip of 64 columns,
+// one lane per column. Columns of up to 1,024 rows are packed into a bit mask
+// in LDS (the waves share the rows), then for every word the first background
+// row at or after it and the last at or before it are found, and the four
+// waves walk their quarters of the rows writing g. So the image is read once
+// and g written once, as 16-bit integers at the start of each row of the
+// output (the FP32 row has room for two). Pass 2 (rows): a workgroup stages
+// one row of g in LDS and every thread searches outward from its column on
+// both sides at once, stopping once a |j - l| reaches the best cost found
+// (phi >= a |j - l|). The row of g is in LDS before any T of the row is
+// written over it; T values are exact integers, stored as FP32 so that T can
+// feed the convolution as a weight image.
 #include "itc_device.h"
 
 namespace itc {
@@ -31,102 +37,120 @@ namespace {
 
 constexpr int CH_ROWS_NT = 256;
 constexpr int CH_ROWS_PER_TASK = 8;
+constexpr int CH_COLS_NT = 256;  // four waves share one strip of 64 columns
+constexpr int CH_COLS_WAVES = CH_COLS_NT / 64;
+constexpr int CH_WORDS = 32;     // columns of up to 32 CH_WORDS rows take the bit-mask pass
 
-__device__ __forceinline__ int phi(int a, int b, int x, int y) {
-  const int mx = x > y ? x : y, mn = x > y ? y : x;
-  return a * mx + (b - a) * mn;
+// g of row i (16-bit, at the start of row i of the output)
+__device__ __forceinline__ uint16_t* g_row(float* t, int64_t pitch, int i) {
+  return reinterpret_cast<uint16_t*>(t + (int64_t)i * pitch);
 }
 
-// Pass 1 for the 64 columns of one strip: lane = column.
-__device__ __forceinline__ void chamfer_cols(const uint8_t* __restrict__ x, int64_t pitch, float* __restrict__ t,
-                                             int H, int W, int v0) {
+// Pass 1, two walks down and up the column (columns taller than the bit-mask
+// pass takes), by the first wave: lane = column.
+__device__ __forceinline__ void chamfer_cols_walk(const uint8_t* __restrict__ x, int64_t pitch,
+                                                  float* __restrict__ t, int H, int W, int v0) {
   const int j = v0 + (int)(threadIdx.x & 63);
-  if (j >= W) return;
+  if (threadIdx.x >= 64 || j >= W) return;
   const uint8_t* xc = x + j;
-  float* tc = t + j;
   int run = 0;  // rows to the nearest background pixel above (row -1 is background)
 #pragma unroll 8
   for (int i = 0; i < H; ++i) {
     run = xc[(int64_t)i * pitch] ? run + 1 : 0;
-    tc[(int64_t)i * pitch] = (float)run;
+    g_row(t, pitch, i)[j] = (uint16_t)run;
   }
   run = 0;  // and below (row H is background)
 #pragma unroll 8
   for (int i = H - 1; i >= 0; --i) {
     run = xc[(int64_t)i * pitch] ? run + 1 : 0;
-    const float up = tc[(int64_t)i * pitch];
-    tc[(int64_t)i * pitch] = fminf(up, (float)run);
+    uint16_t* gp = g_row(t, pitch, i) + j;
+    const int up = *gp;
+    *gp = (uint16_t)(up < run ? up : run);
   }
 }
 
-// Pass 1 for columns of at most 32 * CH_WORDS rows: the column is read once
-// into a bit mask (bit k of word w: row 32w + k is foreground) and the first
-// background row at or after each word is found walking the words upwards;
-// then one walk down the rows writes g, each row needing only its own word.
-// Every LDS word belongs to one lane, so no synchronisation is needed.
-constexpr int CH_WORDS = 32;
-
+// Pass 1 with the bit mask: bit k of word w is row 32 w + k (rows >= H and
+// columns >= W are background). LDS: sbits, snext (first background row at or
+// after word w, H if none), slast (last background row at or before the end
+// of word w, -1 if none), each [CH_WORDS][64].
 __device__ __forceinline__ void chamfer_cols_bits(const uint8_t* __restrict__ x, int64_t pitch,
                                                   float* __restrict__ t, int H, int W, int v0,
-                                                  uint32_t* __restrict__ sbits, int32_t* __restrict__ snext) {
-  const int lane = (int)(threadIdx.x & 63);
+                                                  uint32_t* __restrict__ sbits, int32_t* __restrict__ snext,
+                                                  int32_t* __restrict__ slast) {
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
   const int j = v0 + lane;
   const bool col = j < W;
-  const uint8_t* xc = x + (col ? j : 0);
+  // byte offsets below 2^31 (the image is smaller than 2 GiB)
+  const rsrc_t xr = make_rsrc(x, (uint32_t)((int64_t)H * pitch));
   const int nw = (H + 31) / 32;
-  for (int w = 0; w < nw; ++w) {
+  for (int w = wave; w < nw; w += CH_COLS_WAVES) {
     uint32_t m = 0u;
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
       const int i = 32 * w + k;
-      const bool fg = col && i < H && xc[(int64_t)i * pitch] != 0;
-      m |= fg ? 1u << k : 0u;
+      if (i < H) {  // uniform
+        const uint32_t off = col ? (uint32_t)((int64_t)i * pitch) + (uint32_t)j : 0x80000000u;
+        m |= buf_load<uint8_t>(xr, off, 0) != 0 ? 1u << k : 0u;
+      }
     }
-    sbits[w * 64 + lane] = m;  // rows >= H stay background
+    sbits[w * 64 + lane] = m;
   }
-  int nxt = H;  // row H is background
-  for (int w = nw - 1; w >= 0; --w) {
-    const uint32_t inv = ~sbits[w * 64 + lane];
-    if (inv) nxt = 32 * w + __builtin_ctz(inv);
-    snext[w * 64 + lane] = nxt;
+  __syncthreads();
+  if (wave == 0) {
+    int nxt = H;  // row H is background
+    for (int w = nw - 1; w >= 0; --w) {
+      const uint32_t inv = ~sbits[w * 64 + lane];
+      if (inv) nxt = 32 * w + __builtin_ctz(inv);
+      snext[w * 64 + lane] = nxt;
+    }
+  } else if (wave == 1) {
+    int lst = -1;  // row -1 is background
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t inv = ~sbits[w * 64 + lane];
+      if (inv) lst = 32 * w + 31 - __builtin_clz(inv);
+      slast[w * 64 + lane] = lst;
+    }
   }
-  if (!col) return;
-  float* tc = t + j;
-  int last = -1;  // row -1 is background
-  for (int w = 0; w < nw; ++w) {
-    const uint32_t m = sbits[w * 64 + lane];
-    const int after = w + 1 < nw ? snext[(w + 1) * 64 + lane] : H;
-    const int kn = min(32, H - 32 * w);
-    for (int k = 0; k < kn; ++k) {
-      const int i = 32 * w + k;
-      int g = 0;
-      if ((m >> k) & 1u) {
+  __syncthreads();
+  const int w0 = nw * wave / CH_COLS_WAVES, w1 = nw * (wave + 1) / CH_COLS_WAVES;
+  if (col) {
+    int last = w0 > 0 ? slast[(w0 - 1) * 64 + lane] : -1;
+    for (int w = w0; w < w1; ++w) {
+      const uint32_t m = sbits[w * 64 + lane];
+      const int after = w + 1 < nw ? snext[(w + 1) * 64 + lane] : H;
+      const int kn = min(32, H - 32 * w);
+      for (int k = 0; k < kn; ++k) {
+        const int i = 32 * w + k;
         const uint32_t inv = ~m >> k;  // background rows at or after i within the word
         const int down = inv ? i + __builtin_ctz(inv) : after;
-        g = min(i - last, down - i);
-      } else {
-        last = i;
+        const int g = min(i - last, down - i);  // 0 on a background row (down == i)
+        last = (m >> k) & 1u ? last : i;
+        g_row(t, pitch, i)[j] = (uint16_t)g;
       }
-      tc[(int64_t)i * pitch] = (float)g;
     }
   }
+  __syncthreads();  // LDS is reused by the next strip
 }
 
-// Pass 2 for rows r0 .. r0 + n - 1 (in place: a row of g is staged in LDS
-// before any of its T values is written).
+// Pass 2 for rows r0 .. r0 + n - 1, in place; gs: one row of g (LDS).
 __device__ __forceinline__ void chamfer_rows(float* __restrict__ t, int64_t pitch, int W, int r0, int n, int a,
-                                             int b, float* __restrict__ gs) {
+                                             int b, uint16_t* __restrict__ gs) {
+  const int c = b - a;
   for (int i = r0; i < r0 + n; ++i) {
     float* tr = t + (int64_t)i * pitch;
-    for (int j = threadIdx.x; j < W; j += blockDim.x) gs[j] = tr[j];
+    const uint16_t* gr = g_row(t, pitch, i);
+    for (int j = threadIdx.x; j < W; j += blockDim.x) gs[j] = gr[j];
     __syncthreads();
     for (int j = threadIdx.x; j < W; j += blockDim.x) {
-      const int gj = (int)gs[j];
-      int best = a * min(j + 1, W - j);  // columns -1 and W are background
-      best = min(best, a * gj);          // this column
+      // columns -1 and W are background, and this column: best <= a (j + 1), a (W - j),
+      // so the search below stays inside 0 .. W - 1
+      int best = a * min(min(j + 1, W - j), (int)gs[j]);
       for (int r = 1; a * r < best; ++r) {
-        if (j - r >= 0) best = min(best, phi(a, b, r, (int)gs[j - r]));
-        if (j + r < W) best = min(best, phi(a, b, r, (int)gs[j + r]));
+        // phi(d, g) = a max(d, g) + (b - a) min(d, g) = max(a g + c d, a d + c g)
+        const int ar = a * r, cr = c * r;
+        const int gl = gs[j - r], gh = gs[j + r];
+        best = min(best, max(a * gl + cr, c * gl + ar));
+        best = min(best, max(a * gh + cr, c * gh + ar));
       }
       tr[j] = (float)best;
     }
@@ -134,45 +158,50 @@ __device__ __forceinline__ void chamfer_rows(float* __restrict__ t, int64_t pitc
   }
 }
 
-__global__ void __launch_bounds__(64) chamfer_cols_kernel(const uint8_t* x, int64_t pitch, float* t, int H, int W) {
+__device__ __forceinline__ void cols_task(const uint8_t* x, int64_t pitch, float* t, int H, int W, int v0,
+                                          uint32_t* sbits, int32_t* snext, int32_t* slast) {
+  if (H <= 32 * CH_WORDS)
+    chamfer_cols_bits(x, pitch, t, H, W, v0, sbits, snext, slast);
+  else
+    chamfer_cols_walk(x, pitch, t, H, W, v0);
+}
+
+__global__ void __launch_bounds__(CH_COLS_NT) chamfer_cols_kernel(const uint8_t* x, int64_t pitch, float* t, int H,
+                                                                  int W) {
   __shared__ uint32_t sbits[CH_WORDS * 64];
   __shared__ int32_t snext[CH_WORDS * 64];
-  if (H <= 32 * CH_WORDS)
-    chamfer_cols_bits(x, pitch, t, H, W, blockIdx.x * 64, sbits, snext);
-  else
-    chamfer_cols(x, pitch, t, H, W, blockIdx.x * 64);
+  __shared__ int32_t slast[CH_WORDS * 64];
+  cols_task(x, pitch, t, H, W, blockIdx.x * 64, sbits, snext, slast);
 }
 
 __global__ void __launch_bounds__(CH_ROWS_NT) chamfer_rows_kernel(float* t, int64_t pitch, int H, int W, int a,
                                                                   int b) {
-  extern __shared__ float gs[];
+  extern __shared__ uint16_t gsh[];
   const int r0 = blockIdx.x * CH_ROWS_PER_TASK;
-  chamfer_rows(t, pitch, W, r0, min(CH_ROWS_PER_TASK, H - r0), a, b, gs);
+  chamfer_rows(t, pitch, W, r0, min(CH_ROWS_PER_TASK, H - r0), a, b, gsh);
 }
 
-__global__ void __launch_bounds__(64) chamfer_cols_batched_kernel(const ImageDesc* __restrict__ images,
-                                                                  const ChamferTask* __restrict__ tasks, int ntasks,
-                                                                  const uint8_t* x, float* t) {
+__global__ void __launch_bounds__(CH_COLS_NT) chamfer_cols_batched_kernel(const ImageDesc* __restrict__ images,
+                                                                          const ChamferTask* __restrict__ tasks,
+                                                                          int ntasks, const uint8_t* x, float* t) {
   __shared__ uint32_t sbits[CH_WORDS * 64];
   __shared__ int32_t snext[CH_WORDS * 64];
+  __shared__ int32_t slast[CH_WORDS * 64];
   for (int k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const ChamferTask c = tasks[k];
     const ImageDesc im = images[c.img];
-    if (im.H <= 32 * CH_WORDS)
-      chamfer_cols_bits(x + im.weight_off, im.pitch, t + im.weight_off, im.H, im.W, c.pos * 64, sbits, snext);
-    else
-      chamfer_cols(x + im.weight_off, im.pitch, t + im.weight_off, im.H, im.W, c.pos * 64);
+    cols_task(x + im.weight_off, im.pitch, t + im.weight_off, im.H, im.W, c.pos * 64, sbits, snext, slast);
   }
 }
 
 __global__ void __launch_bounds__(CH_ROWS_NT) chamfer_rows_batched_kernel(const ImageDesc* __restrict__ images,
                                                                           const ChamferTask* __restrict__ tasks,
                                                                           int ntasks, float* t, int a, int b) {
-  extern __shared__ float gs[];
+  extern __shared__ uint16_t gsh[];
   for (int k = blockIdx.x; k < ntasks; k += gridDim.x) {
     const ChamferTask c = tasks[k];
     const ImageDesc im = images[c.img];
-    chamfer_rows(t + im.weight_off, im.pitch, im.W, c.pos, min(CH_ROWS_PER_TASK, im.H - c.pos), a, b, gs);
+    chamfer_rows(t + im.weight_off, im.pitch, im.W, c.pos, min(CH_ROWS_PER_TASK, im.H - c.pos), a, b, gsh);
   }
 }
 
@@ -181,20 +210,20 @@ __global__ void __launch_bounds__(CH_ROWS_NT) chamfer_rows_batched_kernel(const 
 int chamfer_rows_per_task() { return CH_ROWS_PER_TASK; }
 
 hipError_t launch_chamfer(const ImageDesc& im, const void* x, float* t, int a, int b, hipStream_t s) {
-  hipLaunchKernelGGL(chamfer_cols_kernel, dim3((im.W + 63) / 64), dim3(64), 0, s, (const uint8_t*)x, im.pitch, t,
-                     im.H, im.W);
+  hipLaunchKernelGGL(chamfer_cols_kernel, dim3((im.W + 63) / 64), dim3(CH_COLS_NT), 0, s, (const uint8_t*)x,
+                     im.pitch, t, im.H, im.W);
   hipLaunchKernelGGL(chamfer_rows_kernel, dim3((im.H + CH_ROWS_PER_TASK - 1) / CH_ROWS_PER_TASK),
-                     dim3(CH_ROWS_NT), (size_t)im.W * sizeof(float), s, t, im.pitch, im.H, im.W, a, b);
+                     dim3(CH_ROWS_NT), (size_t)im.W * sizeof(uint16_t), s, t, im.pitch, im.H, im.W, a, b);
   return hipGetLastError();
 }
 
 hipError_t launch_chamfer_batched(const ImageDesc* d_images, const ChamferTask* d_cols, int ncols,
                                   const ChamferTask* d_rows, int nrows, int w_max, const void* x, float* t, int a,
                                   int b, int grid_cols, int grid_rows, hipStream_t s) {
-  hipLaunchKernelGGL(chamfer_cols_batched_kernel, dim3(grid_cols), dim3(64), 0, s, d_images, d_cols, ncols,
+  hipLaunchKernelGGL(chamfer_cols_batched_kernel, dim3(grid_cols), dim3(CH_COLS_NT), 0, s, d_images, d_cols, ncols,
                      (const uint8_t*)x, t);
-  hipLaunchKernelGGL(chamfer_rows_batched_kernel, dim3(grid_rows), dim3(CH_ROWS_NT), (size_t)w_max * sizeof(float),
-                     s, d_images, d_rows, nrows, t, a, b);
+  hipLaunchKernelGGL(chamfer_rows_batched_kernel, dim3(grid_rows), dim3(CH_ROWS_NT),
+                     (size_t)w_max * sizeof(uint16_t), s, d_images, d_rows, nrows, t, a, b);
   return hipGetLastError();
 }
 

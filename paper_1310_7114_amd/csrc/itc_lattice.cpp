@@ -227,6 +227,7 @@ struct itc_plan {
   std::vector<itc::ChamferTask> ch_cols, ch_rows;
   bool all_u8 = true;
   int w_max = 0;
+  int h_max = 0;
   itc::ChamferTask* d_ch_cols = nullptr;
   itc::ChamferTask* d_ch_rows = nullptr;
 };
@@ -575,6 +576,7 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
       for (int v0 = 0; v0 < im.W; v0 += 64) p->gtiles.push_back(itc::GradTile{i, u0, v0, 0});
     p->all_u8 = p->all_u8 && im.wdtype == ITC_U8;
     p->w_max = std::max(p->w_max, im.W);
+    p->h_max = std::max(p->h_max, im.H);
     for (int st2 = 0; st2 < im.nstrips; ++st2) p->ch_cols.push_back(itc::ChamferTask{i, st2});
     // row groups shared by the chamfer row pass and the labelling (equal heights, checked below)
     for (int r0 = 0; r0 < im.H; r0 += itc::chamfer_rows_per_task()) p->ch_rows.push_back(itc::ChamferTask{i, r0});
@@ -1119,6 +1121,8 @@ itc_status itc_lattice_chamfer(const itc_lattice_desc* d, const void* x, int32_t
   if (d->weight_dtype != ITC_U8) return fail(ITC_E_ARG, "the chamfer transform takes ITC_U8 images");
   if (d->width > ITC_MAX_CHAMFER_WIDTH)
     return fail(ITC_E_UNSUPPORTED, "width %d exceeds %d", d->width, ITC_MAX_CHAMFER_WIDTH);
+  if (d->height > ITC_MAX_CHAMFER_HEIGHT)
+    return fail(ITC_E_UNSUPPORTED, "height %d exceeds %d", d->height, ITC_MAX_CHAMFER_HEIGHT);
   if ((uint64_t)d->height * (uint64_t)d->pitch >= (1ull << 31))
     return fail(ITC_E_UNSUPPORTED, "image exceeds 2^31 elements");
   itc_status st = check_chamfer_mask(a, b);
@@ -1140,10 +1144,12 @@ itc_status itc_lattice_chamfer_batched(itc_plan* p, const void* weights, int32_t
   if (!p->all_u8) return fail(ITC_E_ARG, "the chamfer transform takes ITC_U8 images");
   if (p->w_max > ITC_MAX_CHAMFER_WIDTH)
     return fail(ITC_E_UNSUPPORTED, "width %d exceeds %d", p->w_max, ITC_MAX_CHAMFER_WIDTH);
+  if (p->h_max > ITC_MAX_CHAMFER_HEIGHT)
+    return fail(ITC_E_UNSUPPORTED, "height %d exceeds %d", p->h_max, ITC_MAX_CHAMFER_HEIGHT);
   itc_status st = check_chamfer_mask(a, b);
   if (st != ITC_OK) return st;
   const int cus = device_cus();
-  const int gc = std::min((int)p->ch_cols.size(), 64 * cus);
+  const int gc = std::min((int)p->ch_cols.size(), 16 * cus);
   const int gr = std::min((int)p->ch_rows.size(), 8 * cus);
   hipError_t e = itc::launch_chamfer_batched(p->d_images, p->d_ch_cols, (int)p->ch_cols.size(), p->d_ch_rows,
                                              (int)p->ch_rows.size(), p->w_max, weights, t_out, a, b, gc, gr,

@@ -165,6 +165,8 @@ def test_chamfer_arguments(itc):
     assert ch(ctypes.byref(df), P, 3, 4, P, None) == 2             # binary images are ITC_U8
     dw = itc.make_desc(2, 16385, 1.0)
     assert ch(ctypes.byref(dw), P, 3, 4, P, None) == 3             # wider than ITC_MAX_CHAMFER_WIDTH
+    dt = itc.make_desc(65536, 4, 1.0)
+    assert ch(ctypes.byref(dt), P, 3, 4, P, None) == 3             # taller than ITC_MAX_CHAMFER_HEIGHT
     dp = itc.make_desc(4, 16, 1.0, pitch=8)
     assert ch(ctypes.byref(dp), P, 3, 4, P, None) == 2             # pitch < width
     assert lib.itc_lattice_chamfer_batched(None, P, 3, 4, P, None) == 1
