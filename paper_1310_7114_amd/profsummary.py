@@ -26,11 +26,30 @@ from collections import defaultdict
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join("paper_1310_7114_amd", "csrc")
 
-# kernel group -> (name fragment, source files whose hash guards the figures)
+SILHOUETTES = ("1400 binary star silhouettes (W 128..1024 x H 128..768, M 10..200, sigma 2/4/8, 100 sweeps), "
+               "FP32, inputs resident in HBM")
+GRAY1024 = ("64 weighted 1024 x 1024 gray images (weights g/255 in FP32, M 256, sigma 4): convolution, D, "
+            "dD/dw and dD/dh, each launched twice (profile_workloads differentiation)")
+GRAY2048 = ("the 2048 x 2048 gray image (M 500, sigma 6): maps and 200 sweeps of the multi-workgroup fit, "
+            "twice (profile_workloads gray2048)")
+SILHOUETTE_PX = 355434824.0
+GRAY1024_PX = 64.0 * 1024 * 1024
+
+# kernel group -> kernel-name prefix (after the namespace), source files whose
+# hash guards the figures, workload, algorithmic HBM bytes per launch (or None)
 GROUPS = {
-    "fit_silhouettes1400": ("fit_batched_kernel", [f"{CSRC}/fit.hip", f"{CSRC}/itc_device.h"]),
-    "conv_silhouettes1400": ("conv_mx_tiles_kernel", [f"{CSRC}/conv_mfma.hip", f"{CSRC}/itc_device.h"]),
+    "fit_silhouettes1400": ("itc::fit_batched_kernel", [f"{CSRC}/fit.hip", f"{CSRC}/itc_device.h"],
+                            SILHOUETTES, None),
+    "conv_silhouettes1400": ("itc::conv_mx_tiles_kernel", [f"{CSRC}/conv_mfma.hip", f"{CSRC}/itc_device.h"],
+                             SILHOUETTES, 13.0 * SILHOUETTE_PX),
+    "conv_valu_gray1024x64": ("itc::conv_tiles_kernel", [f"{CSRC}/conv.hip", f"{CSRC}/itc_device.h"],
+                              GRAY1024, 16.0 * GRAY1024_PX),
+    "adjoint_gray1024x64": ("itc::grad_weights_tiles_kernel", [f"{CSRC}/adjoint.hip", f"{CSRC}/itc_device.h"],
+                            GRAY1024, 8.0 * GRAY1024_PX),
+    "fit_wide_gray2048": ("itc::fit_wide_kernel", [f"{CSRC}/fit_wide.hip", f"{CSRC}/itc_device.h"],
+                          GRAY2048, None),
 }
+HBM_PEAK = 8.0e12
 
 
 def source_sha256(files) -> str:
@@ -86,11 +105,12 @@ def copy_kernel_value(per, expected_kib: float):
 SECONDARY = {
     "volume_96x192x256": ("3-D lattice maps and fit: 96 x 192 x 256 ellipsoid volume, sigma 2, M 64, 50 sweeps",
                           ["vol_"]),
-    "literal_shapes512": ("Algorithm 1 on the 512 x 512 shapes with the paper's widths (M 100, 20 and 0 sweeps)",
-                          ["literal_"]),
     "recursive_gray2048": ("recursive Gaussian maps of the 2048 x 2048 gray image, sigma 4, 16 and 40",
                            ["rec_"]),
     "chamfer_silhouettes1400": ("chamfer transform of the 1400 silhouettes (batched)", ["chamfer_"]),
+    "literal_shapes512_silhouette49": ("Algorithm 1 with the paper's widths: the 512 x 512 shapes (M 100, masks) "
+                                       "and silhouette 49 of the batch (M 17, xi 15.6, recursive P), 20 and 0 "
+                                       "sweeps each", ["literal_"]),
     "segments_silhouettes1400": ("nearest-codevector labels of the 1400 silhouettes (batched)", ["label_"]),
 }
 
@@ -127,6 +147,7 @@ def main():
     ap.add_argument("--calib-mib", type=float)
     ap.add_argument("--commands", required=True, help="text file with the commands that produced the runs")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--groups", nargs="*", default=None, help="write only these kernel groups")
     a = ap.parse_args()
     if a.secondary:
         secondary(a.trace, a.commands, a.out)
@@ -143,13 +164,14 @@ def main():
     sw = exp_kib / cw if cw else None
     commands = open(a.commands).read().strip()
     os.makedirs(a.out, exist_ok=True)
-    for group, (frag, files) in GROUPS.items():
-        names = sorted(k for k in stats if frag in k)
+    for group, (prefix, files, title, algo) in GROUPS.items():
+        if a.groups and group not in a.groups:
+            continue
+        names = sorted(k for k in stats if k.startswith(prefix + "<") or k == prefix)
         if not names:
             continue
-        lines = [f"# {frag}: silhouettes-1400 workload", "",
-                 "1400 binary star silhouettes (W 128..1024 x H 128..768, M 10..200, sigma 2/4/8, 100 sweeps),",
-                 "FP32, inputs resident in HBM. Produced by these commands, from the repository root:", "",
+        lines = [f"# {prefix.split('::')[-1]}: {group}", "", title + ".",
+                 "Produced by these commands, from the repository root:", "",
                  "```", commands, "```", "",
                  "| kernel | calls | average us | total us |", "|---|---|---|---|"]
         for k in names:
@@ -170,6 +192,11 @@ def main():
             total_w += wb
             lines.append(f"| {k} | {fv:.0f} | {wv:.0f} | {fb + wb:.4g} |")
         avg_launch = sum(stats[k][1] for k in names)
+        if algo:
+            gbs = algo / (avg_launch * 1e-6) / 1e9
+            lines += ["", f"Roofline: {algo:.6g} algorithmic HBM bytes per launch / {avg_launch:.1f} us = "
+                          f"{gbs:.0f} GB/s, {gbs * 1e9 / HBM_PEAK:.3f} of 8 TB/s; counted traffic "
+                          f"{(total_f + total_w) / algo:.3f} x the algorithmic bytes."]
         lines += ["", "Figures read by bench.py (valid while the kernel sources hash to source_sha256):", "",
                   f"- source_files: {' '.join(files)}",
                   f"- source_sha256: {source_sha256(files)}",
