@@ -5,26 +5,29 @@
 // with g[t] = exp(-t^2/(2 sigma^2)), tg[t] = t g[t], |t| <= R, and FP64
 // partial sums of S_X = sum I A (one per wave and SX_ROWS-row group).
 //
-// Work decomposition (gfx950): a workgroup of two waves owns a strip of 64
-// columns (lane = column) and a segment of rows, and streams down it in
-// chunks of 16 rows. Per chunk:
+// Work decomposition (gfx950): a workgroup of CONV_WAVES = 4 waves owns a
+// strip of 64 columns (lane = column) and a segment of rows, and streams down
+// it in chunks of 16 rows. Per chunk:
 //   1. staging: the chunk's 16 input rows, with an R-column halo on each side,
 //      are converted to the real type and written to LDS. Their global loads
 //      were issued one chunk earlier into registers, behind the arithmetic;
 //   2. row pass (along v): each lane makes 4 adjacent columns of R0 = I*g and
-//      R1 = I*tg for 2 rows and writes them into an LDS ring holding the last
-//      2R + 16 rows (a whole number of 16-row blocks);
+//      R1 = I*tg for one row (16 lanes per row, four rows per wave) and
+//      writes them into an LDS ring holding the last 2R + 16 rows (a whole
+//      number of 16-row blocks);
 //   3. column pass (along u, R rows behind the row pass): wave w makes rows
-//      8w..8w+7 of the chunk for its lane's column: A, M_u, M_v (24
+//      4w..4w+3 of the chunk for its lane's column: A, M_u, M_v (12
 //      accumulators). A 16-row block of the ring never wraps, and the block
 //      and offset of every read are compile-time for a given w, so each read
 //      is one base register plus an immediate offset. Outputs are stored in
 //      the maps' panel layout; h*A is summed per lane in FP64 and per wave
 //      into the S_X partial of each SX_ROWS-row group.
-// Two waves per workgroup keep two waves on every SIMD at the LDS budget of
-// one ring, so one wave's LDS, scalar and memory instructions issue beside
-// the other's FMAs. Taps are computed once per segment in FP64 (one lane per
-// tap) and held in scalar registers; tap loops are unrolled for the class.
+// Four waves per workgroup share one ring: at the LDS budget of one ring the
+// chip holds twice the waves of a two-wave workgroup (the FP32 convolution of
+// 64 x 1024^2 images took 0.47 ms against 0.56 ms with two), so one wave's
+// LDS, scalar and memory instructions issue beside the others' FMAs. Taps
+// are computed once per segment in FP64 (one lane per tap) and held in scalar
+// registers; tap loops are unrolled for the class.
 #include "itc_device.h"
 
 namespace itc {
@@ -93,7 +96,7 @@ __device__ __forceinline__ void with_weight_type(int wdtype, F&& f) {
     f(double{});
 }
 
-// Column pass of one wave: rows 8w..8w+7 of the chunk whose window starts at
+// Column pass of one wave: rows KB w .. KB w + KB - 1 of the chunk whose window starts at
 // ring block `jb` (chunk index minus J0).
 template <typename T, int R, int WV>
 __device__ __forceinline__ void column_pass(const T* __restrict__ ring0, const T* __restrict__ ring1, int jb,
@@ -172,7 +175,7 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
     }
   }
 
-  // ---- staging: wave w fetches rows 8w..8w+7 of a chunk, columns c = lane and lane + 64 ----
+  // ---- staging: wave w fetches rows KB w .. KB w + KB - 1 of a chunk, columns c = lane and lane + 64 ----
   const int col0 = v0 - R + lane, col1 = col0 + CONV_TW;
   const bool ok0 = col0 >= 0 && col0 < W;
   const bool ok1 = lane + CONV_TW < G::XW && col1 >= 0 && col1 < W;
@@ -231,8 +234,10 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
   // byte offset of row 0 of this lane's column in the panel layout; rows are MAP_PANEL elements apart
   const uint32_t mvoff = (uint32_t)map_index(H, 0, col) * (uint32_t)sizeof(T);
   constexpr uint32_t rowstep = MAP_PANEL * sizeof(T);
+  constexpr int SPW = SX_SLOTS / CONV_WAVES;  // S_X slots per wave
+  static_assert(SPW * CONV_WAVES == SX_SLOTS, "the S_X slots divide among the waves");
   double* part = reinterpret_cast<double*>(mbase + im.map_off + im.part_off) +
-                 (int64_t)strip * im.nsxg * SX_SLOTS + 2 * wave;
+                 (int64_t)strip * im.nsxg * SX_SLOTS + SPW * wave;
   double sxd = 0.0;  // this lane's share of the current S_X row group
 
   const int rq = lane >> 4, cg = lane & 15;  // row pass: row in a set of 4, column group of 4
@@ -283,7 +288,7 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
     }
     __syncthreads();
 
-    // ---------------- column pass: rows 8w..8w+7 of output chunk j - J0 ----------------
+    // ---------------- column pass: rows KB w .. KB w + KB - 1 of output chunk j - J0 ----------------
     if (j >= G::J0) {
       const int o0 = s0 + (j - G::J0) * CH + wave * KB;
       if (o0 < seg_end) {
@@ -301,10 +306,16 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
           }
         });
         T a[KB], mu[KB], mv[KB];
-        if (wave == 0)
-          column_pass<T, R, 0>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
-        else
-          column_pass<T, R, 1>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+        switch (wave) {  // uniform; the window offset of each wave is compile-time
+          case 0: column_pass<T, R, 0>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv); break;
+          case 1: column_pass<T, R, 1>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv); break;
+          case 2:
+            if constexpr (CONV_WAVES > 2) column_pass<T, R, 2>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+            break;
+          default:
+            if constexpr (CONV_WAVES > 3) column_pass<T, R, 3>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+            break;
+        }
         T hv[KB];
         with_weight_type(wdtype, [&](auto wt) {
           using WT = decltype(wt);
@@ -328,14 +339,15 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
         sxd += (double)sx;
       }
       // the last chunk of an S_X row group (or of the segment): wave w writes
-      // slot 2w of the group's partials and clears slot 2w + 1
+      // the first of its slots of the group's partials and clears the others
       const int jo = j - G::J0;
       if ((jo + 1) % (SX_ROWS / CH) == 0 || jo == n_out - 1) {  // uniform
         const double tot = wave_sum(sxd);
         const int g = (s0 + jo * CH) / SX_ROWS;
         if (lane == 0) {
           part[(int64_t)g * SX_SLOTS] = tot * (double)im.scale;
-          part[(int64_t)g * SX_SLOTS + 1] = 0.0;
+#pragma unroll
+          for (int q = 1; q < SPW; ++q) part[(int64_t)g * SX_SLOTS + q] = 0.0;
         }
         sxd = 0.0;
       }

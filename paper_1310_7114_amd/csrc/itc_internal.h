@@ -14,7 +14,10 @@ namespace itc {
 // ---------------------------------------------------------------------------
 constexpr int CONV_TW = 64;     // strip width = one wave of lanes
 constexpr int CONV_CH = 16;     // rows per chunk
-constexpr int CONV_WAVES = 2;   // waves per workgroup, sharing one strip
+#ifndef ITC_CONV_WAVES
+#define ITC_CONV_WAVES 4
+#endif
+constexpr int CONV_WAVES = ITC_CONV_WAVES;  // waves per workgroup, sharing one strip
 constexpr int CONV_NT = 64 * CONV_WAVES;
 constexpr int CONV_KB = CONV_CH / CONV_WAVES;  // output rows per lane per chunk
 constexpr int ITC_MAX_CODEVECTORS_DEV = 1024;
