@@ -369,14 +369,18 @@ __global__ void __launch_bounds__(CONV_NT) conv_image_kernel(ImageDesc im, int S
 
 // ---------------------------------------------------------------------------
 // batched: persistent workgroups of one radius class walk its tile list
-// (cost-sorted by the planner)
+// (cost-sorted by the planner, split into one sublist per XCD: block b walks
+// sublist b mod CONV_XCDS, so the strips of a segment row, whose input
+// windows overlap, read those lines through one L2)
 // ---------------------------------------------------------------------------
 template <typename T, int R>
 __global__ void __launch_bounds__(CONV_NT) conv_tiles_kernel(const ImageDesc* __restrict__ images,
-                                                             const ConvTile* __restrict__ tiles,
-                                                             int ntiles, const char* wbase, char* mbase) {
+                                                             const ConvTile* __restrict__ tiles, XcdSplit xs,
+                                                             const char* wbase, char* mbase) {
   __shared__ __align__(16) char smem[ConvGeom<T, R>::SMEM];
-  for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+  const int x = blockIdx.x % CONV_XCDS, nx = gridDim.x / CONV_XCDS;
+  const int end = xs.beg[x + 1];
+  for (int i = xs.beg[x] + (int)blockIdx.x / CONV_XCDS; i < end; i += nx) {
     const ConvTile t = tiles[i];
     const ImageDesc im = images[t.img];
     conv_segment<T, R>(im, t.strip, t.s0, t.S, wbase, mbase, smem);
@@ -435,17 +439,18 @@ hipError_t launch_conv_image(bool f64, const ImageDesc& im, const void* w, void*
 }
 
 hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, const ConvTile* d_tiles,
-                             int ntiles, const void* w, void* m, int grid, hipStream_t s) {
+                             const XcdSplit& xs, const void* w, void* m, int grid, hipStream_t s) {
   if (rclass >= CONV_MX_CLASS) return hipErrorInvalidValue;  // launched by launch_conv_mx_tiles
+  if (grid % CONV_XCDS != 0) return hipErrorInvalidValue;
 #define ITC_CASE_F(RR)                                                                              \
   case RR:                                                                                         \
     hipLaunchKernelGGL((conv_tiles_kernel<float, RR>), dim3(grid), dim3(CONV_NT), 0, s, d_images,    \
-                       d_tiles, ntiles, (const char*)w, (char*)m);                                  \
+                       d_tiles, xs, (const char*)w, (char*)m);                                      \
     return hipGetLastError();
 #define ITC_CASE_D(RR)                                                                              \
   case RR:                                                                                         \
     hipLaunchKernelGGL((conv_tiles_kernel<double, RR>), dim3(grid), dim3(CONV_NT), 0, s, d_images,   \
-                       d_tiles, ntiles, (const char*)w, (char*)m);                                  \
+                       d_tiles, xs, (const char*)w, (char*)m);                                      \
     return hipGetLastError();
   if (f64) {
     switch (rclass) { ITC_FOR_CLASSES_F64(ITC_CASE_D) default: return hipErrorInvalidValue; }

@@ -118,7 +118,7 @@ hipError_t launch_conv_image(bool f64, const ImageDesc& h_image, const void* wei
                              hipStream_t s);
 // Persistent launch over `ntiles` tiles of one radius class.
 hipError_t launch_conv_tiles(bool f64, int rclass, const ImageDesc* d_images, const ConvTile* d_tiles,
-                             int ntiles, const void* weights, void* maps, int grid, hipStream_t s);
+                             const XcdSplit& xs, const void* weights, void* maps, int grid, hipStream_t s);
 // Resident workgroups per compute unit of the persistent kernels (0 on error).
 int conv_tiles_blocks_per_cu(bool f64, int rclass);
 int fit_blocks_per_cu(bool f64, int m_max, int max_passes);

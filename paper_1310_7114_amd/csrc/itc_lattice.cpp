@@ -208,7 +208,7 @@ struct itc_plan {
   std::vector<ConvTile> tiles;
   std::vector<int> cls;
   std::vector<int> launch_key, launch_begin, launch_end, launch_grid;
-  itc::XcdSplit mx_split;  // XCD sublists of the matrix-core launch (offsets from its first tile)
+  std::vector<itc::XcdSplit> launch_split;  // XCD sublists of each launch (offsets from its first tile)
   int mx_max_ra = 0;  // largest aligned radius of the matrix-core images
   // convolution tile shape per class key (set by the autotuning hook; 0 =
   // default): target segment rows and workgroups per compute unit
@@ -239,10 +239,10 @@ struct itc_plan {
 // vector-ALU class is one persistent launch; the matrix-core classes share
 // one persistent launch, largest radius first (a workgroup then changes its
 // ring layout only a few times), with the fewest workgroups per compute unit
-// any of them asks for. Its tiles are split into one sublist per XCD: every
-// segment row of an image (the strips whose input windows overlap) goes
-// whole to the XCD with the least cost so far, so the overlapping input
-// lines are read into one L2.
+// any of them asks for. Every launch's tiles are split into one sublist per
+// XCD: every segment row of an image (the strips whose input windows
+// overlap) goes whole to the XCD with the least cost so far, so the
+// overlapping input lines are read into one L2.
 constexpr int PLAN_NKEYS = itc::CONV_MX_CLASS + 33;
 constexpr int PLAN_SEG_DEFAULT = 256, PLAN_SEG_MIN = 64, PLAN_SEG_MAX = 4096;
 
@@ -285,6 +285,7 @@ static void build_conv_tiles(itc_plan* p) {
   p->launch_begin.clear();
   p->launch_end.clear();
   p->launch_grid.clear();
+  p->launch_split.clear();
   const int cus = device_cus();
   auto append_sorted = [&](int key) {
     std::vector<int> idx(by_class[key].size());
@@ -292,27 +293,9 @@ static void build_conv_tiles(itc_plan* p) {
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cost_of[key][a] > cost_of[key][c]; });
     for (int k : idx) p->tiles.push_back(by_class[key][k]);
   };
-  for (int key = 0; key < PLAN_NKEYS; ++key)
-    if (!by_class[key].empty()) p->cls.push_back(key);
-  for (int key = 0; key < itc::CONV_MX_CLASS; ++key) {
-    if (by_class[key].empty()) continue;
-    p->launch_key.push_back(key);
-    p->launch_begin.push_back((int)p->tiles.size());
-    append_sorted(key);
-    p->launch_end.push_back((int)p->tiles.size());
-    const int per = p->key_per[key] > 0 ? p->key_per[key] : class_occupancy(p, key);
-    p->launch_grid.push_back(std::min(p->launch_end.back() - p->launch_begin.back(), per * cus));
-  }
-  const int begin = (int)p->tiles.size();
-  int per = class_occupancy(p, itc::CONV_MX_CLASS);
-  for (int key = PLAN_NKEYS - 1; key >= itc::CONV_MX_CLASS; --key) {
-    if (by_class[key].empty()) continue;
-    append_sorted(key);
-    if (p->key_per[key] > 0) per = std::min(per, p->key_per[key]);
-  }
-  if ((int)p->tiles.size() > begin) {
-    // deal segment rows (runs of tiles of one image and segment, adjacent
-    // after the sort) to the XCD sublists, least loaded first
+  // deal the segment rows of tiles [begin, end) (runs of tiles of one image
+  // and segment, adjacent after the sort) to the XCD sublists, least loaded first
+  auto deal_xcd = [&](int begin) {
     std::vector<std::vector<ConvTile>> sub(itc::CONV_XCDS);
     std::vector<int64_t> load(itc::CONV_XCDS, 0);
     for (int a = begin; a < (int)p->tiles.size();) {
@@ -320,7 +303,8 @@ static void build_conv_tiles(itc_plan* p) {
       int64_t cost = 0;
       while (b < (int)p->tiles.size() && p->tiles[b].img == p->tiles[a].img && p->tiles[b].s0 == p->tiles[a].s0) {
         const ImageDesc& im = p->images[p->tiles[b].img];
-        cost += std::min(p->tiles[b].S, im.H - p->tiles[b].s0) + 2 * itc::conv_mx_radius(im.rclass);
+        const int halo = class_key_of(im) >= itc::CONV_MX_CLASS ? itc::conv_mx_radius(im.rclass) : im.rclass;
+        cost += std::min(p->tiles[b].S, im.H - p->tiles[b].s0) + 2 * halo;
         ++b;
       }
       const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -329,17 +313,41 @@ static void build_conv_tiles(itc_plan* p) {
       a = b;
     }
     p->tiles.resize(begin);
+    itc::XcdSplit xs{};
     for (int x = 0; x < itc::CONV_XCDS; ++x) {
-      p->mx_split.beg[x] = (int)p->tiles.size() - begin;
+      xs.beg[x] = (int)p->tiles.size() - begin;
       p->tiles.insert(p->tiles.end(), sub[x].begin(), sub[x].end());
     }
-    p->mx_split.beg[itc::CONV_XCDS] = (int)p->tiles.size() - begin;
-    const int grid = std::max(itc::CONV_XCDS, per * cus / itc::CONV_XCDS * itc::CONV_XCDS);
-    p->launch_key.push_back(itc::CONV_MX_CLASS + p->mx_max_ra);
+    xs.beg[itc::CONV_XCDS] = (int)p->tiles.size() - begin;
+    return xs;
+  };
+  auto add_launch = [&](int key, int begin, int per) {
+    const itc::XcdSplit xs = deal_xcd(begin);
+    p->launch_key.push_back(key);
     p->launch_begin.push_back(begin);
     p->launch_end.push_back((int)p->tiles.size());
-    p->launch_grid.push_back(grid);
+    // no more workgroups than tiles (rounded to whole XCD rounds), at most `per` per compute unit
+    const int ntiles = (int)p->tiles.size() - begin;
+    const int grid = std::min(per * cus, (ntiles + itc::CONV_XCDS - 1) / itc::CONV_XCDS * itc::CONV_XCDS);
+    p->launch_grid.push_back(std::max(itc::CONV_XCDS, grid / itc::CONV_XCDS * itc::CONV_XCDS));
+    p->launch_split.push_back(xs);
+  };
+  for (int key = 0; key < PLAN_NKEYS; ++key)
+    if (!by_class[key].empty()) p->cls.push_back(key);
+  for (int key = 0; key < itc::CONV_MX_CLASS; ++key) {
+    if (by_class[key].empty()) continue;
+    const int begin = (int)p->tiles.size();
+    append_sorted(key);
+    add_launch(key, begin, p->key_per[key] > 0 ? p->key_per[key] : class_occupancy(p, key));
   }
+  const int begin = (int)p->tiles.size();
+  int per = class_occupancy(p, itc::CONV_MX_CLASS);
+  for (int key = PLAN_NKEYS - 1; key >= itc::CONV_MX_CLASS; --key) {
+    if (by_class[key].empty()) continue;
+    append_sorted(key);
+    if (p->key_per[key] > 0) per = std::min(per, p->key_per[key]);
+  }
+  if ((int)p->tiles.size() > begin) add_launch(itc::CONV_MX_CLASS + p->mx_max_ra, begin, per);
 }
 
 extern "C" {
@@ -737,10 +745,9 @@ itc_status itc_lattice_precompute_batched(itc_plan* p, const void* weights, void
     hipError_t e =
         key >= itc::CONV_MX_CLASS
             ? itc::launch_conv_mx_tiles(key - itc::CONV_MX_CLASS, p->d_images, p->d_tiles + p->launch_begin[l],
-                                        p->mx_split, weights, maps, p->launch_grid[l], (hipStream_t)stream)
-            : itc::launch_conv_tiles(false, key, p->d_images, p->d_tiles + p->launch_begin[l],
-                                     p->launch_end[l] - p->launch_begin[l], weights, maps, p->launch_grid[l],
-                                     (hipStream_t)stream);
+                                        p->launch_split[l], weights, maps, p->launch_grid[l], (hipStream_t)stream)
+            : itc::launch_conv_tiles(false, key, p->d_images, p->d_tiles + p->launch_begin[l], p->launch_split[l],
+                                     weights, maps, p->launch_grid[l], (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "batched convolution launch");
   }
   return ok();
