@@ -28,7 +28,7 @@
 // are private to the wave (LDS operations of one wave complete in order: no
 // barrier). Per chunk:
 //   1. staging (shared): the chunk's 16 input rows with their column halo,
-//      fetched two chunks earlier as aligned 4-byte words, are converted to
+//      fetched MX_AHEAD (4) chunks earlier as aligned 4-byte words, are converted to
 //      FP16 into one of two LDS buffers. One barrier per chunk.
 //   2. row pass: K/32 A-fragments (16 rows x 32 columns) times the tap
 //      fragments -> R0, R1 for 16 rows x 16 columns; scaled, split and
@@ -46,6 +46,7 @@
 // its XCD; a workgroup clears its shared memory when the radius of its next
 // tile differs from the last one's.
 #include <type_traits>
+#include <utility>
 
 #include "itc_device.h"
 
@@ -60,6 +61,11 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MX_NT = 256;  // four waves; wave w owns strip columns 16w..16w+15
 constexpr int MX_CH = 16;   // rows per chunk
+#ifndef ITC_MX_AHEAD
+#define ITC_MX_AHEAD 4
+#endif
+constexpr int MX_AHEAD = ITC_MX_AHEAD;  // chunks whose input loads are in flight (2..4)
+static_assert(MX_AHEAD >= 2 && MX_AHEAD <= 4, "prefetch depth");
 // Cache policy of the map stores: non-temporal (the maps are written once
 // and read much later, after every other image's maps have streamed past).
 constexpr int MX_STREAM = 2;
@@ -88,6 +94,12 @@ struct MxGeom {
   static_assert(NB * MX_CH >= MX_CH + 2 * RA, "ring holds a column window");
   static_assert(SW % 4 == 0 && RA % 4 == 0, "word-aligned staging");
 };
+
+// f(integral_constant<int, I>) for I = 0, 1, ... in order
+template <typename F, int... I>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
 
 __device__ __forceinline__ f4_t mfma(h8_t a, h8_t b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -186,10 +198,11 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     ioff[i] = item ? r * G::SWP + 4 * d : -1;  // halves into a staging buffer
     imask[i] = !ok ? 0u : (keep >= 4 ? 0xffffffffu : (1u << (8 * keep)) - 1u);
   }
-  // Two chunks are in flight: set P = j & 1 holds chunk j from two chunks
-  // before it is staged (P is a template constant so the sets stay in
-  // registers), which leaves the loads two chunks of work to arrive.
-  uint32_t pre[2][G::NI];
+  // MX_AHEAD chunks are in flight: set P = j mod MX_AHEAD holds chunk j from
+  // MX_AHEAD chunks before it is staged (P is a template constant so the sets
+  // stay in registers), which leaves the loads that many chunks of work to
+  // arrive.
+  uint32_t pre[MX_AHEAD][G::NI];
   auto fetch = [&](int j, auto P) {
     constexpr int p = decltype(P)::value;
 #pragma unroll
@@ -200,9 +213,9 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
       pre[p][i] = __builtin_amdgcn_raw_buffer_load_b32(wres, off, 0, 0);
     }
   };
-  auto stage_chunk = [&](auto P) {
+  auto stage_chunk = [&](auto P, auto B) {
     constexpr int p = decltype(P)::value;
-    _Float16* xs = stage + p * G::STAGE;
+    _Float16* xs = stage + decltype(B)::value * G::STAGE;
 #pragma unroll
     for (int i = 0; i < G::NI; ++i) {
       if (G::NI * MX_NT == MX_CH * G::SWD || ioff[i] >= 0) {
@@ -237,14 +250,14 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
 
   // One chunk: stage j, row pass j, column pass j - J0 (before the first
   // output chunk its results are discarded).
-  auto chunk = [&](int j, auto P) {
-    stage_chunk(P);
+  auto chunk = [&](int j, auto P, auto B) {
+    stage_chunk(P, B);
     __syncthreads();
-    fetch(j + 2, P);  // past the last chunk: rows outside the image, masked
+    fetch(j + MX_AHEAD, P);  // past the last chunk: rows outside the image, masked
 
     // ---------------- row pass: chunk j -> ring block j mod NB ----------------
     {
-      const _Float16* xs = stage + decltype(P)::value * G::STAGE + n * G::SWP + 16 * wave + 8 * q;
+      const _Float16* xs = stage + decltype(B)::value * G::STAGE + n * G::SWP + 16 * wave + 8 * q;
       f4_t r0 = {0.f, 0.f, 0.f, 0.f}, r1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < G::KS; ++s) {
@@ -255,7 +268,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         r1 = mfma(a, t_lo[s], r1);
       }
       // stored weights of row n, columns 4q..4q+3 of this wave, for S_X
-      const h4_t xh = *reinterpret_cast<const h4_t*>(stage + decltype(P)::value * G::STAGE + n * G::SWP + RA +
+      const h4_t xh = *reinterpret_cast<const h4_t*>(stage + decltype(B)::value * G::STAGE + n * G::SWP + RA +
                                                       16 * wave + 4 * q);
       uint32_t hb = 0u;
 #pragma unroll
@@ -339,17 +352,23 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     }
   };
 
-  using P0 = std::integral_constant<int, 0>;
-  using P1 = std::integral_constant<int, 1>;
-  fetch(0, P0{});
-  fetch(1, P1{});
-  chunk(0, P0{});  // peeled, so that the loop is entered with the same pending operations as it repeats
+  // chunk j takes prefetch set j mod MX_AHEAD and staging buffer j mod 2;
+  // the loop is unrolled over lcm(MX_AHEAD, 2) chunks so that both are
+  // template constants
+  constexpr int U = MX_AHEAD % 2 == 0 ? MX_AHEAD : 2 * MX_AHEAD;
+  using Seq = std::make_integer_sequence<int, U>;
+  auto at = [&](int j, auto I) {
+    constexpr int c = 1 + decltype(I)::value;  // j = 1 mod U
+    chunk(j, std::integral_constant<int, c % MX_AHEAD>{}, std::integral_constant<int, c % 2>{});
+  };
+  for_each_index([&](auto I) { fetch(decltype(I)::value, I); }, std::make_integer_sequence<int, MX_AHEAD>{});
+  // peeled, so that the loop is entered with the same pending operations as it repeats
+  chunk(0, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
   int j = 1;
-  for (; j + 1 < nchunks; j += 2) {
-    chunk(j, P1{});
-    chunk(j + 1, P0{});
-  }
-  if (j < nchunks) chunk(j, P1{});
+  for (; j + U - 1 < nchunks; j += U) for_each_index([&](auto I) { at(j + decltype(I)::value, I); }, Seq{});
+  for_each_index([&](auto I) {
+    if (decltype(I)::value < U - 1 && j + decltype(I)::value < nchunks) at(j + decltype(I)::value, I);
+  }, Seq{});
 }
 
 // Zero the rings once per workgroup: column passes of warm-up chunks read
