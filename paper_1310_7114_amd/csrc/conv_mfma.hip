@@ -28,7 +28,7 @@
 // are private to the wave (LDS operations of one wave complete in order: no
 // barrier). Per chunk:
 //   1. staging (shared): the chunk's 16 input rows with their column halo,
-//      fetched MX_AHEAD (4) chunks earlier as aligned 4-byte words, are converted to
+//      fetched MX_AHEAD (10) chunks earlier as aligned 4-byte words, are converted to
 //      FP16 into one of two LDS buffers. One barrier per chunk.
 //   2. row pass: K/32 A-fragments (16 rows x 32 columns) times the tap
 //      fragments -> R0, R1 for 16 rows x 16 columns; scaled, split and
@@ -62,10 +62,15 @@ typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 constexpr int MX_NT = 256;  // four waves; wave w owns strip columns 16w..16w+15
 constexpr int MX_CH = 16;   // rows per chunk
 #ifndef ITC_MX_AHEAD
-#define ITC_MX_AHEAD 4
+#define ITC_MX_AHEAD 10
 #endif
-constexpr int MX_AHEAD = ITC_MX_AHEAD;  // chunks whose input loads are in flight (2..4)
-static_assert(MX_AHEAD >= 2 && MX_AHEAD <= 4, "prefetch depth");
+// Chunks whose input loads are in flight. The memory counter that a wave
+// waits on counts loads and stores in issue order, so a chunk's loads are
+// complete only when the map stores issued before them are too: the depth
+// also sets how many chunks of stores a wave keeps in flight. At most 63
+// operations can be counted: MX_AHEAD (NI + 3) stays below that.
+constexpr int MX_AHEAD = ITC_MX_AHEAD;
+static_assert(MX_AHEAD >= 2 && MX_AHEAD <= 16, "prefetch depth");
 // Cache policy of the map stores: non-temporal (the maps are written once
 // and read much later, after every other image's maps have streamed past).
 constexpr int MX_STREAM = 2;
@@ -86,13 +91,17 @@ struct MxGeom {
   static constexpr int SWD = SW / 4;             // staged 4-byte words per row
   static constexpr int SWP = SW + 8;             // staged row pitch
   static constexpr int NI = (MX_CH * SWD + MX_NT - 1) / MX_NT;  // staged words per thread and chunk
-  static constexpr size_t STAGE = (size_t)MX_CH * SWP;     // halves per staging buffer
+  static constexpr size_t STAGE = (size_t)MX_CH * SWP;     // halves of staged rows per buffer
+  static constexpr int NDUM = NI * MX_NT - MX_CH * SWD;     // thread items past the chunk's words
+  static constexpr size_t STAGEB = STAGE + 4 * NDUM;        // halves per buffer, with a slot per such item
   static constexpr size_t RINGA = (size_t)CONV_TW * RINGP;  // halves per ring array
   static constexpr int HROWS = NB * MX_CH;                   // rows of a wave's weight ring (16 bytes each)
-  static constexpr size_t SMEM = (2 * STAGE + 4 * RINGA) * sizeof(_Float16) + (size_t)4 * HROWS * 16;
+  static constexpr size_t SMEM = (2 * STAGEB + 4 * RINGA) * sizeof(_Float16) + (size_t)4 * HROWS * 16;
   static_assert(RINGP / 2 % 8 == 4 && SWP / 2 % 8 == 4, "bank-spread pitches");
   static_assert(NB * MX_CH >= MX_CH + 2 * RA, "ring holds a column window");
   static_assert(SW % 4 == 0 && RA % 4 == 0, "word-aligned staging");
+  static_assert(STAGEB % 8 == 0, "16-byte aligned staging buffers and rings");
+  static_assert(MX_AHEAD * (NI + 3) <= 63, "pending memory operations within the counter's range");
 };
 
 // f(integral_constant<int, I>) for I = 0, 1, ... in order
@@ -120,8 +129,8 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
                                            const char* __restrict__ wbase, char* __restrict__ mbase,
                                            _Float16* __restrict__ smem) {
   using G = MxGeom<RA>;
-  _Float16* stage = smem;                  // [2][16][SWP]
-  _Float16* ring = smem + 2 * G::STAGE;    // [4][64][RINGP]: R0 hi, R0 lo, R1 hi, R1 lo
+  _Float16* stage = smem;                  // [2][STAGEB]: 16 rows of SWP halves, then the item slots
+  _Float16* ring = smem + 2 * G::STAGEB;   // [4][64][RINGP]: R0 hi, R0 lo, R1 hi, R1 lo
   uint32_t* hring = reinterpret_cast<uint32_t*>(ring + 4 * G::RINGA);  // [4 waves][HROWS][4 words]
 
   // lane-derived values are recomputed per segment: an opaque thread index
@@ -195,7 +204,10 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     const int keep = W - x;  // bytes of the word inside the image
     irow[i] = ok ? r : -(1 << 20);             // never inside the image: the load reads 0
     icol[i] = x;
-    ioff[i] = item ? r * G::SWP + 4 * d : -1;  // halves into a staging buffer
+    // halves into a staging buffer; items past the chunk write zeros to a
+    // slot of their own past the staged rows, so that the staging stores
+    // are unconditional and the compiler keeps each load where it is issued
+    ioff[i] = item ? r * G::SWP + 4 * d : (int)G::STAGE + 4 * (idx - MX_CH * G::SWD);
     imask[i] = !ok ? 0u : (keep >= 4 ? 0xffffffffu : (1u << (8 * keep)) - 1u);
   }
   // MX_AHEAD chunks are in flight: set P = j mod MX_AHEAD holds chunk j from
@@ -215,18 +227,16 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
   };
   auto stage_chunk = [&](auto P, auto B) {
     constexpr int p = decltype(P)::value;
-    _Float16* xs = stage + decltype(B)::value * G::STAGE;
+    _Float16* xs = stage + decltype(B)::value * G::STAGEB;
 #pragma unroll
     for (int i = 0; i < G::NI; ++i) {
-      if (G::NI * MX_NT == MX_CH * G::SWD || ioff[i] >= 0) {
-        const uint32_t v = pre[p][i] & imask[i];
-        h4_t h;
-        h[0] = (_Float16)(float)(v & 0xffu);
-        h[1] = (_Float16)(float)((v >> 8) & 0xffu);
-        h[2] = (_Float16)(float)((v >> 16) & 0xffu);
-        h[3] = (_Float16)(float)(v >> 24);
-        *reinterpret_cast<h4_t*>(xs + ioff[i]) = h;
-      }
+      const uint32_t v = pre[p][i] & imask[i];
+      h4_t h;
+      h[0] = (_Float16)(float)(v & 0xffu);
+      h[1] = (_Float16)(float)((v >> 8) & 0xffu);
+      h[2] = (_Float16)(float)((v >> 16) & 0xffu);
+      h[3] = (_Float16)(float)(v >> 24);
+      *reinterpret_cast<h4_t*>(xs + ioff[i]) = h;
     }
   };
 
@@ -257,7 +267,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
 
     // ---------------- row pass: chunk j -> ring block j mod NB ----------------
     {
-      const _Float16* xs = stage + decltype(B)::value * G::STAGE + n * G::SWP + 16 * wave + 8 * q;
+      const _Float16* xs = stage + decltype(B)::value * G::STAGEB + n * G::SWP + 16 * wave + 8 * q;
       f4_t r0 = {0.f, 0.f, 0.f, 0.f}, r1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < G::KS; ++s) {
@@ -268,7 +278,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
         r1 = mfma(a, t_lo[s], r1);
       }
       // stored weights of row n, columns 4q..4q+3 of this wave, for S_X
-      const h4_t xh = *reinterpret_cast<const h4_t*>(stage + decltype(B)::value * G::STAGE + n * G::SWP + RA +
+      const h4_t xh = *reinterpret_cast<const h4_t*>(stage + decltype(B)::value * G::STAGEB + n * G::SWP + RA +
                                                       16 * wave + 4 * q);
       uint32_t hb = 0u;
 #pragma unroll
@@ -361,7 +371,19 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
     constexpr int c = 1 + decltype(I)::value;  // j = 1 mod U
     chunk(j, std::integral_constant<int, c % MX_AHEAD>{}, std::integral_constant<int, c % 2>{});
   };
-  for_each_index([&](auto I) { fetch(decltype(I)::value, I); }, std::make_integer_sequence<int, MX_AHEAD>{});
+  // Each prologue fetch is followed by as many (discarded) stores as a loop
+  // chunk issues after its fetch, so that the loop is entered with the same
+  // sequence of pending memory operations as it repeats. The compiler's
+  // memory-counter waits at the loop head are the smallest over the entry and
+  // the back edge: without the padding, the shorter prologue sequence would
+  // cut the loads in flight in the first chunks of every loop iteration.
+  for_each_index([&](auto I) {
+    fetch(decltype(I)::value, I);
+    asm volatile("" ::: "memory");  // keeps the padding stores distinct and in place
+#pragma unroll
+    for (int d = 0; d < 3; ++d) __builtin_amdgcn_raw_buffer_store_b32(0u, resA, MX_DISCARD + 16u * d, 0, 0);
+    asm volatile("" ::: "memory");
+  }, std::make_integer_sequence<int, MX_AHEAD>{});
   // peeled, so that the loop is entered with the same pending operations as it repeats
   chunk(0, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
   int j = 1;
@@ -377,7 +399,7 @@ __device__ __forceinline__ void mx_segment(const ImageDesc& im, int strip, int s
 template <int RA>
 __device__ __forceinline__ void mx_clear_rings(_Float16* smem) {
   using G = MxGeom<RA>;
-  uint32_t* p = reinterpret_cast<uint32_t*>(smem + 2 * G::STAGE);
+  uint32_t* p = reinterpret_cast<uint32_t*>(smem + 2 * G::STAGEB);
   constexpr int nwords = (int)((4 * G::RINGA * sizeof(_Float16) + (size_t)4 * G::HROWS * 16) / 4);
   for (int i = threadIdx.x; i < nwords; i += MX_NT) p[i] = 0u;
   __syncthreads();
