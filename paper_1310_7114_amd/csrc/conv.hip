@@ -32,6 +32,15 @@
 
 namespace itc {
 
+#ifndef ITC_CONV_AHEAD
+#define ITC_CONV_AHEAD 1
+#endif
+// Chunks whose loads are in flight. A wave's memory counter counts loads and
+// stores in issue order, and at most 63 of them: each chunk issues 3 KB loads
+// and 3 KB stores.
+constexpr int CONV_AHEAD = ITC_CONV_AHEAD;
+static_assert(CONV_AHEAD >= 1 && CONV_AHEAD * 6 * CONV_KB <= 63, "pending memory operations within the counter");
+
 template <typename T, int R>
 struct ConvGeom {
   static constexpr int CH = CONV_CH;
@@ -134,8 +143,8 @@ __device__ __forceinline__ void column_pass(const T* __restrict__ ring0, const T
   }
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int s0, int S,
+template <typename T, int R, typename WT>
+__device__ __forceinline__ void conv_segment_t(const ImageDesc& im, int strip, int s0, int S,
                                              const char* __restrict__ wbase, char* __restrict__ mbase,
                                              char* __restrict__ smem) {
   using G = ConvGeom<T, R>;
@@ -155,8 +164,7 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
   const int origin = s0 - R;                 // absolute row of relative row 0
   const int need_end = min(H, seg_end + R);  // row-pass rows at or past this are never read
 
-  const int wdtype = im.wdtype;
-  const int esz = wdtype == 0 ? 1 : (wdtype == 1 ? 4 : 8);
+  constexpr int esz = (int)sizeof(WT);
   const uint32_t rowbytes = (uint32_t)(im.pitch * esz);
   const rsrc_t wres = make_rsrc(wbase + im.weight_off, (uint32_t)H * rowbytes);
   const rsrc_t mres = make_rsrc(mbase + im.map_off, (uint32_t)(3 * im.plane * (int64_t)sizeof(T)));
@@ -175,62 +183,10 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
     }
   }
 
-  // ---- staging: wave w fetches rows KB w .. KB w + KB - 1 of a chunk, columns c = lane and lane + 64 ----
-  const int col0 = v0 - R + lane, col1 = col0 + CONV_TW;
-  const bool ok0 = col0 >= 0 && col0 < W;
-  const bool ok1 = lane + CONV_TW < G::XW && col1 >= 0 && col1 < W;
-  const uint32_t off0 = ok0 ? (uint32_t)col0 : 0u, off1 = ok1 ? (uint32_t)col1 : 0u;
-  Raw raw0[KB], raw1[KB];
-  auto fetch = [&](int j) {
-    const int y0 = origin + j * CH + wave * KB;
-    with_weight_type(wdtype, [&](auto wt) {
-      using WT = decltype(wt);
-      const uint32_t b0 = off0 * (uint32_t)sizeof(WT), b1 = off1 * (uint32_t)sizeof(WT);
-      if (y0 >= 0 && y0 + KB <= H) {  // all rows inside: loads at clamped columns, then select
-        uint32_t so = (uint32_t)y0 * rowbytes;
-#pragma unroll
-        for (int r = 0; r < KB; ++r) {
-          const Raw a0 = load_raw<T, WT>(wres, b0, so);
-          const Raw a1 = load_raw<T, WT>(wres, b1, so);
-          raw0[r] = ok0 ? a0 : (Raw)0;
-          raw1[r] = ok1 ? a1 : (Raw)0;
-          so += rowbytes;
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < KB; ++r) {
-          const int y = y0 + r;
-          const bool in = y >= 0 && y < H;
-          const uint32_t so = in ? (uint32_t)y * rowbytes : 0u;
-          Raw a0 = (Raw)0, a1 = (Raw)0;
-          if (in) {
-            a0 = load_raw<T, WT>(wres, b0, so);
-            a1 = load_raw<T, WT>(wres, b1, so);
-          }
-          raw0[r] = ok0 ? a0 : (Raw)0;
-          raw1[r] = ok1 ? a1 : (Raw)0;
-        }
-      }
-    });
-  };
-  // every lane writes both of its staged columns (columns >= XW are never read)
-  auto stage = [&]() {
-    T* x = xin + wave * KB * G::XP + lane;
-    with_weight_type(wdtype, [&](auto wt) {
-      using WT = decltype(wt);
-#pragma unroll
-      for (int r = 0; r < KB; ++r) {
-        x[r * G::XP] = raw_value<T, WT>(raw0[r]) * scale;
-        x[r * G::XP + CONV_TW] = raw_value<T, WT>(raw1[r]) * scale;
-      }
-    });
-  };
-
   const uint32_t planeb = (uint32_t)(im.plane * (int64_t)sizeof(T));  // bytes per plane
   const int col = v0 + lane;
   const bool col_ok = col < W;
   const bool col_stored = col < im.npanels * MAP_PANEL;  // the strip may reach past the last panel
-  const uint32_t hoff = col_ok ? (uint32_t)col : 0u;
   // byte offset of row 0 of this lane's column in the panel layout; rows are MAP_PANEL elements apart
   const uint32_t mvoff = (uint32_t)map_index(H, 0, col) * (uint32_t)sizeof(T);
   constexpr uint32_t rowstep = MAP_PANEL * sizeof(T);
@@ -240,13 +196,71 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
                  (int64_t)strip * im.nsxg * SX_SLOTS + SPW * wave;
   double sxd = 0.0;  // this lane's share of the current S_X row group
 
+  // ---- loads of chunk j, issued CONV_AHEAD chunks before it is staged ----
+  // Wave w loads rows KB w .. KB w + KB - 1 of the chunk's input (columns
+  // lane and lane + 64 of the staged window) and the stored weights of its
+  // own output rows of chunk j (lane's column, for S_X). Columns and rows
+  // outside the image (or past the rows the segment reads) load at BUF_OOB,
+  // which reads 0, so no branch or select waits on a load before its use.
+  const int col0 = v0 - R + lane, col1 = col0 + CONV_TW;
+  const bool ok0 = col0 >= 0 && col0 < W;
+  const bool ok1 = lane + CONV_TW < G::XW && col1 >= 0 && col1 < W;
+  // per-lane column terms of the offsets, and bit 31 for the lanes outside the image
+  const uint32_t c0 = ok0 ? (uint32_t)col0 : 0u, c1 = ok1 ? (uint32_t)col1 : 0u, cc = col_ok ? (uint32_t)col : 0u;
+  const uint32_t bad0 = (uint32_t)!ok0 << 31, bad1 = (uint32_t)!ok1 << 31, badc = (uint32_t)!col_ok << 31;
+  constexpr int AH = CONV_AHEAD;
+  Raw raw0[AH][KB], raw1[AH][KB], hraw[AH][KB];
+  auto fetch = [&](int j, auto P) {
+    constexpr int p = decltype(P)::value;
+    const int y0 = origin + j * CH + wave * KB;         // input rows
+    const int h0 = s0 + (j - G::J0) * CH + wave * KB;  // output rows
+    {
+      constexpr uint32_t es = sizeof(WT);
+#pragma unroll
+      for (int r = 0; r < KB; ++r) {
+        const int y = y0 + r, o = h0 + r;
+        // offsets below 2^31 inside the image; bit 31 set (BUF_OOB or above) outside it
+        const uint32_t yout = (uint32_t)(y < 0 || y >= need_end) << 31;  // uniform
+        const uint32_t oout = (uint32_t)(o < s0 || o >= seg_end) << 31;   // uniform
+        const uint32_t yb = (yout ? 0u : (uint32_t)y * rowbytes) | yout;
+        const uint32_t ob = (oout ? 0u : (uint32_t)o * rowbytes) | oout;
+        raw0[p][r] = load_raw<T, WT>(wres, (yb + c0 * es) | bad0, 0);
+        raw1[p][r] = load_raw<T, WT>(wres, (yb + c1 * es) | bad1, 0);
+        hraw[p][r] = load_raw<T, WT>(wres, (ob + cc * es) | badc, 0);
+      }
+    }
+  };
+  // every lane writes both of its staged columns (columns >= XW are never
+  // read) and converts the S_X weights of its output rows: set P is free
+  // for the loads of a later chunk after this
+  auto stage = [&](auto P, T (&hv)[KB]) {
+    constexpr int p = decltype(P)::value;
+    T* x = xin + wave * KB * G::XP + lane;
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+      x[r * G::XP] = raw_value<T, WT>(raw0[p][r]) * scale;
+      x[r * G::XP + CONV_TW] = raw_value<T, WT>(raw1[p][r]) * scale;
+      hv[r] = raw_value<T, WT>(hraw[p][r]);
+    }
+  };
+  // as many (dropped) stores as a column pass makes: the prologue and the
+  // warm-up chunks issue them, so that every chunk of the loop leaves the same
+  // sequence of pending memory operations and the compiler's memory-counter
+  // waits allow CONV_AHEAD chunks of loads in flight
+  auto pad_stores = [&]() {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < 3 * KB; ++k) buf_store<T>((T)0, mres, BUF_OOB + 16u * k, 0);
+    asm volatile("" ::: "memory");
+  };
+
   const int rq = lane >> 4, cg = lane & 15;  // row pass: row in a set of 4, column group of 4
 
-  fetch(0);
-  for (int j = 0; j < nchunks; ++j) {
-    stage();
+  auto chunk = [&](int j, auto P) {
+    T hv[KB];
+    stage(P, hv);
     __syncthreads();
-    if (j + 1 < nchunks) fetch(j + 1);
+    fetch(j + AH, P);
 
     // ---------------- row pass: ring rows of chunk j ----------------
     {
@@ -289,70 +303,70 @@ __device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int
     __syncthreads();
 
     // ---------------- column pass: rows KB w .. KB w + KB - 1 of output chunk j - J0 ----------------
-    if (j >= G::J0) {
-      const int o0 = s0 + (j - G::J0) * CH + wave * KB;
-      if (o0 < seg_end) {
-        Raw hraw[KB];  // weights of the output rows for S_X, loaded before the arithmetic
-        with_weight_type(wdtype, [&](auto wt) {
-          using WT = decltype(wt);
-          const uint32_t hb = hoff * (uint32_t)sizeof(WT);
-          uint32_t so = (uint32_t)o0 * rowbytes;
-#pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            Raw v = (Raw)0;
-            if (o0 + k < H) v = load_raw<T, WT>(wres, hb, so);
-            hraw[k] = col_ok ? v : (Raw)0;
-            so += rowbytes;
-          }
-        });
-        T a[KB], mu[KB], mv[KB];
-        switch (wave) {  // uniform; the window offset of each wave is compile-time
-          case 0: column_pass<T, R, 0>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv); break;
-          case 1: column_pass<T, R, 1>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv); break;
-          case 2:
-            if constexpr (CONV_WAVES > 2) column_pass<T, R, 2>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
-            break;
-          default:
-            if constexpr (CONV_WAVES > 3) column_pass<T, R, 3>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
-            break;
-        }
-        T hv[KB];
-        with_weight_type(wdtype, [&](auto wt) {
-          using WT = decltype(wt);
-#pragma unroll
-          for (int k = 0; k < KB; ++k) hv[k] = raw_value<T, WT>(hraw[k]);
-        });
-        // columns past the width inside the last panel are stored too (never
-        // read); they carry zero weight for S_X
-        T sx = (T)0;
-        uint32_t so = (uint32_t)o0 * rowstep;
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-          if (o0 + k < seg_end && col_stored) {
-            buf_store<T>(a[k], mres, mvoff, so);
-            buf_store<T>(mu[k], mres, mvoff, so + planeb);
-            buf_store<T>(mv[k], mres, mvoff, so + 2 * planeb);
-          }
-          if (o0 + k < seg_end) sx = fma_t(hv[k], a[k], sx);
-          so += rowstep;
-        }
-        sxd += (double)sx;
-      }
-      // the last chunk of an S_X row group (or of the segment): wave w writes
-      // the first of its slots of the group's partials and clears the others
-      const int jo = j - G::J0;
-      if ((jo + 1) % (SX_ROWS / CH) == 0 || jo == n_out - 1) {  // uniform
-        const double tot = wave_sum(sxd);
-        const int g = (s0 + jo * CH) / SX_ROWS;
-        if (lane == 0) {
-          part[(int64_t)g * SX_SLOTS] = tot * (double)im.scale;
-#pragma unroll
-          for (int q = 1; q < SPW; ++q) part[(int64_t)g * SX_SLOTS + q] = 0.0;
-        }
-        sxd = 0.0;
-      }
+    if (j < G::J0) {  // uniform: warm-up chunk, nothing to store
+      pad_stores();
+      return;
     }
-  }
+    const int o0 = s0 + (j - G::J0) * CH + wave * KB;
+    T a[KB], mu[KB], mv[KB];
+    switch (wave) {  // uniform; the window offset of each wave is compile-time
+      case 0: column_pass<T, R, 0>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv); break;
+      case 1: column_pass<T, R, 1>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv); break;
+      case 2:
+        if constexpr (CONV_WAVES > 2) column_pass<T, R, 2>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+        break;
+      default:
+        if constexpr (CONV_WAVES > 3) column_pass<T, R, 3>(ring0, ring1, j - G::J0, lane, g, tg, a, mu, mv);
+        break;
+    }
+    // columns past the width inside the last panel are stored too (never
+    // read); they carry zero weight for S_X. Rows past the segment store at
+    // BUF_OOB (dropped).
+    T sx = (T)0;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const bool row_ok = o0 + k < seg_end;  // uniform
+      const uint32_t off = (mvoff + (uint32_t)(o0 + k) * rowstep) | ((uint32_t)!(row_ok && col_stored) << 31);
+      buf_store<T>(a[k], mres, off, 0);
+      buf_store<T>(mu[k], mres, off, planeb);
+      buf_store<T>(mv[k], mres, off, 2 * planeb);
+      if (row_ok) sx = fma_t(hv[k], a[k], sx);
+    }
+    sxd += (double)sx;
+    // the last chunk of an S_X row group (or of the segment): wave w writes
+    // the first of its slots of the group's partials and clears the others
+    const int jo = j - G::J0;
+    if ((jo + 1) % (SX_ROWS / CH) == 0 || jo == n_out - 1) {  // uniform
+      const double tot = wave_sum(sxd);
+      const int gi = (s0 + jo * CH) / SX_ROWS;
+      if (lane == 0) {
+        part[(int64_t)gi * SX_SLOTS] = tot * (double)im.scale;
+#pragma unroll
+        for (int q = 1; q < SPW; ++q) part[(int64_t)gi * SX_SLOTS + q] = 0.0;
+      }
+      sxd = 0.0;
+    }
+  };
+
+  for_each_index([&](auto I) {
+    fetch(decltype(I)::value, I);
+    pad_stores();
+  }, std::make_integer_sequence<int, AH>{});
+  int j = 0;
+  for (; j + AH <= nchunks; j += AH)
+    for_each_index([&](auto I) { chunk(j + decltype(I)::value, I); }, std::make_integer_sequence<int, AH>{});
+  for_each_index([&](auto I) {
+    if (j + decltype(I)::value < nchunks) chunk(j + decltype(I)::value, I);
+  }, std::make_integer_sequence<int, AH>{});
+}
+
+// One segment for the image's stored weight type (one uniform branch per
+// segment, so the loop carries no type switch).
+template <typename T, int R>
+__device__ __forceinline__ void conv_segment(const ImageDesc& im, int strip, int s0, int S,
+                                             const char* __restrict__ wbase, char* __restrict__ mbase,
+                                             char* __restrict__ smem) {
+  with_weight_type(im.wdtype, [&](auto wt) { conv_segment_t<T, R, decltype(wt)>(im, strip, s0, S, wbase, mbase, smem); });
 }
 
 // ---------------------------------------------------------------------------

@@ -104,12 +104,6 @@ struct MxGeom {
   static_assert(MX_AHEAD * (NI + 3) <= 63, "pending memory operations within the counter's range");
 };
 
-// f(integral_constant<int, I>) for I = 0, 1, ... in order
-template <typename F, int... I>
-__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-
 __device__ __forceinline__ f4_t mfma(h8_t a, h8_t b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }

@@ -347,8 +347,7 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
       }
     }
     // ---- S_XW, S_W: fixed-order block reduction in FP64 ----
-    sxw = wave_sum(sxw);
-    sw = wave_sum(sw);
+    wave_sum2(sxw, sw);
     if (lane == 0) {
       red[2 * wave] = sxw;
       red[2 * wave + 1] = sw;
@@ -364,9 +363,9 @@ __device__ void fit_image(const ImageDesc& im, const FitImageArgs& a, char* smem
     const bool sums_ok = isfinite(S_XW) && isfinite(S_W);  // uniform
     const bool final_eval = last || !sums_ok;
     if (!sums_ok) flags |= FIT_STATUS_SUMS;
-    if (tid == 0 && (a.d_trace || (final_eval && a.d_out) || a.status)) {
+    if (tid == 0 && (a.d_trace || (final_eval && (a.d_out || a.status)))) {
       const double D = log(S_W) + log(a.s_x) - 2.0 * log(S_XW);
-      if (!isfinite(D)) flags |= FIT_STATUS_D;
+      if (final_eval && !isfinite(D)) flags |= FIT_STATUS_D;
       if (a.d_trace) a.d_trace[t] = D;
       if (final_eval && a.d_out) *a.d_out = D;
     }
@@ -454,13 +453,17 @@ __global__ void __launch_bounds__(FIT_NT) fit_image_kernel(ImageDesc im, FitArgs
   fit_image<T, MAXPASS>(im, a, smem);
 }
 
+// Workgroup g fits the images sched[G + 1 + sched[g]] .. sched[G + 1 + sched[g + 1] - 1]
+// (G workgroups: the first G + 1 entries are the offsets of each workgroup's list).
 template <typename T, int MAXPASS>
 __global__ void __launch_bounds__(FIT_NT) fit_batched_kernel(const ImageDesc* __restrict__ images,
-                                                             const int32_t* __restrict__ order, FitArgs fa) {
+                                                             const int32_t* __restrict__ sched, FitArgs fa) {
   extern __shared__ __align__(16) char smem[];
   double* red = reinterpret_cast<double*>(smem);
-  for (int ii = blockIdx.x; ii < fa.n; ii += gridDim.x) {
-    const int i = order[ii];
+  const int32_t* list = sched + gridDim.x + 1;
+  const int end = sched[blockIdx.x + 1];
+  for (int ii = sched[blockIdx.x]; ii < end; ++ii) {
+    const int i = list[ii];
     const ImageDesc im = images[i];
     // S_X: the fixed-order sum of the FP64 partials written with the maps
     const double* sxp = reinterpret_cast<const double*>((const char*)fa.maps + im.map_off + im.part_off);
@@ -512,31 +515,31 @@ int fit_blocks_per_cu(bool f64, int m_max, int max_passes) {
 }
 
 template <typename T, int MP>
-static void launch_fit_t(const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a, int grid,
+static void launch_fit_t(const ImageDesc* d_images, const int32_t* d_sched, const FitArgs& a, int grid,
                          hipStream_t s, const ImageDesc* h_image) {
   if (h_image)
     hipLaunchKernelGGL((fit_image_kernel<T, MP>), dim3(1), dim3(FIT_NT), fit_smem(h_image->M), s, *h_image, a);
   else
     hipLaunchKernelGGL((fit_batched_kernel<T, MP>), dim3(grid), dim3(FIT_NT), fit_smem(a.m_max), s, d_images,
-                       d_order, a);
+                       d_sched, a);
 }
 
-hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
+hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_sched, const FitArgs& a,
                       int grid, hipStream_t s, const ImageDesc* h_image) {
   // passes are bounded by the largest codebook of the launch (in the
   // gradient-only mode as well, which runs the same per-image code)
   switch (h_image ? maxpass_for(h_image->M) : (a.max_passes > 0 ? maxpass_bound(a.max_passes) : 4)) {
     case 1:
-      f64 ? launch_fit_t<double, 1>(d_images, d_order, a, grid, s, h_image)
-          : launch_fit_t<float, 1>(d_images, d_order, a, grid, s, h_image);
+      f64 ? launch_fit_t<double, 1>(d_images, d_sched, a, grid, s, h_image)
+          : launch_fit_t<float, 1>(d_images, d_sched, a, grid, s, h_image);
       break;
     case 2:
-      f64 ? launch_fit_t<double, 2>(d_images, d_order, a, grid, s, h_image)
-          : launch_fit_t<float, 2>(d_images, d_order, a, grid, s, h_image);
+      f64 ? launch_fit_t<double, 2>(d_images, d_sched, a, grid, s, h_image)
+          : launch_fit_t<float, 2>(d_images, d_sched, a, grid, s, h_image);
       break;
     default:
-      f64 ? launch_fit_t<double, 4>(d_images, d_order, a, grid, s, h_image)
-          : launch_fit_t<float, 4>(d_images, d_order, a, grid, s, h_image);
+      f64 ? launch_fit_t<double, 4>(d_images, d_sched, a, grid, s, h_image)
+          : launch_fit_t<float, 4>(d_images, d_sched, a, grid, s, h_image);
       break;
   }
   return hipGetLastError();

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "itc_internal.h"
 
 namespace itc {
@@ -35,21 +37,30 @@ __device__ __forceinline__ double lane_value(double x, int l) {
   return __builtin_bit_cast(double, v);
 }
 
+// f(integral_constant<int, I>) for I = 0, 1, ... in order (compile-time indices
+// for register arrays in unrolled loops)
+template <typename F, int... I>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Cross-lane moves through DPP (data-parallel primitives of the VALU): no LDS
-// round trip, so a whole-wave reduction costs a few VALU latencies.
+// round trip, so a whole-wave reduction costs a few VALU latencies. Lanes of
+// rows that ROWS leaves out are not written and hold undefined values: the
+// reductions below read their result from lanes that every step writes.
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ double dpp_f64(double x) {
   int2 v = __builtin_bit_cast(int2, x);
-  v.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, ROWS, 0xf, false);
-  v.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, ROWS, 0xf, false);
+  v.x = __builtin_amdgcn_mov_dpp(v.x, CTRL, ROWS, 0xf, false);
+  v.y = __builtin_amdgcn_mov_dpp(v.y, CTRL, ROWS, 0xf, false);
   return __builtin_bit_cast(double, v);
 }
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ float dpp_f32(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, ROWS, 0xf, false));
 }
 // DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror,
 // row_mirror, row_bcast:15 (into rows 1 and 3), row_bcast:31 (into rows 2, 3).
@@ -65,6 +76,24 @@ __device__ __forceinline__ double wave_sum(double x) {
   x += dpp_f64<DPP_BCAST15, 0xa>(x);
   x += dpp_f64<DPP_BCAST31, 0xc>(x);
   return lane_value(x, 63);
+}
+// Two independent wave sums in the same order as wave_sum, interleaved so
+// that each step's cross-lane moves of one overlap the other's addition.
+__device__ __forceinline__ void wave_sum2(double& a, double& b) {
+  a += dpp_f64<DPP_QP_1032>(a);
+  b += dpp_f64<DPP_QP_1032>(b);
+  a += dpp_f64<DPP_QP_2301>(a);
+  b += dpp_f64<DPP_QP_2301>(b);
+  a += dpp_f64<DPP_HALF_MIRROR>(a);
+  b += dpp_f64<DPP_HALF_MIRROR>(b);
+  a += dpp_f64<DPP_MIRROR>(a);
+  b += dpp_f64<DPP_MIRROR>(b);
+  a += dpp_f64<DPP_BCAST15, 0xa>(a);
+  b += dpp_f64<DPP_BCAST15, 0xa>(b);
+  a += dpp_f64<DPP_BCAST31, 0xc>(a);
+  b += dpp_f64<DPP_BCAST31, 0xc>(b);
+  a = lane_value(a, 63);
+  b = lane_value(b, 63);
 }
 // Sum over aligned groups of P lanes (P a power of two); every lane of a group
 // gets the same value (each step adds a commutative pair).
@@ -102,11 +131,16 @@ __device__ __forceinline__ float wave_max_nonneg(float x) {
 
 // ---------------------------------------------------------------------------
 // Buffer access: a uniform base in a resource descriptor, a per-lane 32-bit
-// byte offset and a uniform 32-bit byte offset (scalar register). Callers keep
-// every access inside [base, base + bytes); the hardware range check is not
-// relied on.
+// byte offset and a uniform 32-bit byte offset (scalar register). The
+// descriptor holds the buffer's size: a load at a per-lane offset of BUF_OOB
+// (past any buffer this library addresses, and the scalar offsets added to it
+// stay below 2^31) returns 0 without a memory request, and a store there is
+// dropped. Kernels use such offsets for the lanes that must not access memory,
+// instead of branches, so that loads stay in flight across the code that
+// follows; every other access stays inside the buffer.
 // ---------------------------------------------------------------------------
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t BUF_OOB = 0x80000000u;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);

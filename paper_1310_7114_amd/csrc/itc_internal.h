@@ -228,7 +228,11 @@ struct FitArgs {
 // Passes of the fit over an image's owned codevectors (1..4).
 int fit_passes_of(int M);
 
-hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_order, const FitArgs& a,
+// Fit of one image (h_image set: one workgroup) or of a batch: `grid`
+// workgroups, workgroup g taking the images d_sched[grid + 1 + k] for k in
+// [d_sched[g], d_sched[g + 1]) (the plan's schedule: grid + 1 list offsets,
+// then the image indices).
+hipError_t launch_fit(bool f64, const ImageDesc* d_images, const int32_t* d_sched, const FitArgs& a,
                       int grid, hipStream_t s, const ImageDesc* h_image);
 
 // The fit of one FP32 image over several workgroups, one launch per sweep:

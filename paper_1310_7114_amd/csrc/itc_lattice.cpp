@@ -214,13 +214,15 @@ struct itc_plan {
   // default): target segment rows and workgroups per compute unit
   std::vector<int> key_seg, key_per;
   size_t tile_cap = 0;  // capacity of d_tiles (the most tiles any shape gives)
-  std::vector<int32_t> order;  // fit order, most expensive first
+  // fit schedule: workgroup g of the fit launch (fit_grid workgroups) takes
+  // the images fit_list[fit_begin[g] .. fit_begin[g + 1]) in turn
+  std::vector<int32_t> fit_begin, fit_list;
   int fit_grid = 1;
   std::vector<itc::GradTile> gtiles;  // 64 x 64 tiles of every image, for dL/dh
   int grad_grid = 1;
   ImageDesc* d_images = nullptr;
   ConvTile* d_tiles = nullptr;
-  int32_t* d_order = nullptr;
+  int32_t* d_sched = nullptr;  // fit_begin then fit_list
   itc::GradTile* d_gtiles = nullptr;
   bool any_mx = false;  // some image runs the matrix-core convolution (4-byte aligned weights base)
   // chamfer transform: column-pass strips and row-pass row groups
@@ -245,6 +247,34 @@ struct itc_plan {
 // overlapping input lines are read into one L2.
 constexpr int PLAN_NKEYS = itc::CONV_MX_CLASS + 33;
 constexpr int PLAN_SEG_DEFAULT = 256, PLAN_SEG_MIN = 64, PLAN_SEG_MAX = 4096;
+
+// Fit schedule: the images, most expensive first, dealt to the F x C
+// workgroups of the launch (F per compute unit, C units) round by round, in
+// alternating directions from one round to the next, so that the most
+// expensive image of one round and the cheapest of the next share a
+// workgroup. Workgroup g's images form the list fit_list[fit_begin[g] ..
+// fit_begin[g + 1]). Results do not depend on the schedule: each image's fit is
+// the same code on one workgroup, wherever it runs.
+static void fit_schedule(itc_plan* p, const std::vector<double>& cost, int C, int F) {
+  const int n = p->n;
+  std::vector<int32_t> sorted(n);
+  std::iota(sorted.begin(), sorted.end(), 0);
+  std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  const int grid = std::min(n, C * F);
+  std::vector<std::vector<int32_t>> lists(grid);
+  for (int r0 = 0; r0 < n; r0 += grid) {
+    const int cnt = std::min(grid, n - r0);
+    const bool rev = (r0 / grid) & 1;
+    for (int q = 0; q < cnt; ++q) lists[rev ? cnt - 1 - q : q].push_back(sorted[r0 + q]);
+  }
+  p->fit_grid = grid;
+  p->fit_begin.assign(1, 0);
+  p->fit_list.clear();
+  for (const auto& l : lists) {
+    p->fit_list.insert(p->fit_list.end(), l.begin(), l.end());
+    p->fit_begin.push_back((int32_t)p->fit_list.size());
+  }
+}
 
 // The matrix-core kernel needs 4-byte aligned rows: a plan checks the image
 // offsets and pitches here and the weights base at every call.
@@ -594,38 +624,25 @@ itc_status itc_lattice_plan_create(const itc_batch* b, itc_plan** out) {
   for (const ImageDesc& im : p->images)
     if (class_key_of(im) >= itc::CONV_MX_CLASS) p->mx_max_ra = std::max(p->mx_max_ra, itc::conv_mx_radius(im.rclass));
   build_conv_tiles(p);
-  p->order.resize(b->n);
-  std::iota(p->order.begin(), p->order.end(), 0);
-  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int c) { return fit_cost[a] > fit_cost[c]; });
-
   const int cus = device_cus();
   int fper = itc::fit_blocks_per_cu(false, p->m_max, p->max_passes);
   if (fper < 1) fper = 1;
-  p->fit_grid = std::min(p->n, fper * cus);
-  {
-    // Workgroup g fits the images at positions g, g + grid, ...: deal the
-    // cost-sorted images to the positions of each round in alternating
-    // directions, so the most expensive of one round and the cheapest of the
-    // next share a workgroup.
-    const std::vector<int32_t> sorted = p->order;
-    const int grid = p->fit_grid;
-    for (int r0 = 0; r0 < p->n; r0 += grid) {
-      const int cnt = std::min(grid, p->n - r0);
-      const bool rev = (r0 / grid) & 1;
-      for (int q = 0; q < cnt; ++q) p->order[r0 + q] = sorted[r0 + (rev ? cnt - 1 - q : q)];
-    }
-  }
+  fit_schedule(p, fit_cost, cus, fper);
   p->grad_grid = std::min((int)p->gtiles.size(), 4 * cus);
   for (const ImageDesc& im : p->images) p->any_mx = p->any_mx || class_key_of(im) >= itc::CONV_MX_CLASS;
 
   hipError_t e = hipMalloc(&p->d_images, sizeof(ImageDesc) * p->n);
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, sizeof(ConvTile) * std::max<size_t>(1, p->tile_cap));
-  if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int32_t) * p->n);
+  if (e == hipSuccess) e = hipMalloc(&p->d_sched, sizeof(int32_t) * (p->fit_begin.size() + p->fit_list.size()));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_images, p->images.data(), sizeof(ImageDesc) * p->n, hipMemcpyHostToDevice);
   if (e == hipSuccess && !p->tiles.empty())
     e = hipMemcpy(p->d_tiles, p->tiles.data(), sizeof(ConvTile) * p->tiles.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), sizeof(int32_t) * p->n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_sched, p->fit_begin.data(), sizeof(int32_t) * p->fit_begin.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_sched + p->fit_begin.size(), p->fit_list.data(), sizeof(int32_t) * p->fit_list.size(),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_gtiles, sizeof(itc::GradTile) * p->gtiles.size());
   if (e == hipSuccess)
     e = hipMemcpy(p->d_gtiles, p->gtiles.data(), sizeof(itc::GradTile) * p->gtiles.size(), hipMemcpyHostToDevice);
@@ -702,7 +719,7 @@ itc_status itc_lattice_divergence_backward_batched(itc_plan* p, const void* maps
     a.max_passes = p->max_passes;
     a.grad_w = grad_w;
     a.grad_d = grad_d;
-    hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, s, nullptr);
+    hipError_t e = itc::launch_fit(false, p->d_images, p->d_sched, a, p->fit_grid, s, nullptr);
     if (e != hipSuccess) return device_fail(e, "batched codebook gradient launch");
   }
   if (grad_weights) {
@@ -725,7 +742,7 @@ void itc_lattice_plan_destroy(itc_plan* p) {
   if (!p) return;
   if (p->d_images) (void)hipFree(p->d_images);
   if (p->d_tiles) (void)hipFree(p->d_tiles);
-  if (p->d_order) (void)hipFree(p->d_order);
+  if (p->d_sched) (void)hipFree(p->d_sched);
   if (p->d_gtiles) (void)hipFree(p->d_gtiles);
   if (p->d_ch_cols) (void)hipFree(p->d_ch_cols);
   if (p->d_ch_rows) (void)hipFree(p->d_ch_rows);
@@ -773,7 +790,7 @@ itc_status itc_lattice_fit_batched(itc_plan* p, const void* maps, const void* w_
   a.m_max = p->m_max;
   a.max_passes = p->max_passes;
   a.write_w = 1;
-  hipError_t e = itc::launch_fit(false, p->d_images, p->d_order, a, p->fit_grid, (hipStream_t)stream, nullptr);
+  hipError_t e = itc::launch_fit(false, p->d_images, p->d_sched, a, p->fit_grid, (hipStream_t)stream, nullptr);
   if (e != hipSuccess) return device_fail(e, "batched fit launch");
   return ok();
 }
