@@ -118,6 +118,18 @@ __device__ __forceinline__ double group_sum(double x) {
   return x;
 }
 
+// Min over the 64 lanes of a wave (NaN lanes are ignored unless all are NaN);
+// every lane gets it.
+__device__ __forceinline__ double wave_min(double x) {
+  x = fmin(x, dpp_f64<DPP_QP_1032>(x));
+  x = fmin(x, dpp_f64<DPP_QP_2301>(x));
+  x = fmin(x, dpp_f64<DPP_HALF_MIRROR>(x));
+  x = fmin(x, dpp_f64<DPP_MIRROR>(x));
+  x = fmin(x, dpp_f64<DPP_BCAST15, 0xa>(x));
+  x = fmin(x, dpp_f64<DPP_BCAST31, 0xc>(x));
+  return lane_value(x, 63);
+}
+
 // Max over the 64 lanes of a wave of non-negative values; every lane gets it.
 __device__ __forceinline__ float wave_max_nonneg(float x) {
   x = fmaxf(x, dpp_f32<DPP_QP_1032>(x));
