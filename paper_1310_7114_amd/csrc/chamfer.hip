@@ -100,16 +100,21 @@ __device__ __forceinline__ void chamfer_cols_bits(const uint8_t* __restrict__ x,
   // byte offsets below 2^31 (the image is smaller than 2 GiB)
   const rsrc_t xr = make_rsrc(x, (uint32_t)((int64_t)H * pitch));
   const int nw = (H + 31) / 32;
+  // a word's 32 loads are issued together: rows past the image and columns
+  // past the width load at an offset with bit 31 set (beyond the buffer),
+  // which reads 0, so no branch makes the compiler wait for each load
+  const uint32_t cbad = (uint32_t)!col << 31;
   for (int w = wave; w < nw; w += CH_COLS_WAVES) {
-    uint32_t m = 0u;
+    uint32_t v[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
       const int i = 32 * w + k;
-      if (i < H) {  // uniform
-        const uint32_t off = col ? (uint32_t)((int64_t)i * pitch) + (uint32_t)j : 0x80000000u;
-        m |= buf_load<uint8_t>(xr, off, 0) != 0 ? 1u << k : 0u;
-      }
+      const uint32_t rbad = (uint32_t)(i >= H) << 31;  // uniform
+      v[k] = buf_load<uint8_t>(xr, ((uint32_t)i * (uint32_t)pitch + (uint32_t)j) | rbad | cbad, 0);
     }
+    uint32_t m = 0u;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) m |= (v[k] != 0u ? 1u : 0u) << k;
     sbits[w * 64 + lane] = m;
   }
   __syncthreads();
