@@ -27,16 +27,6 @@ constexpr int LB_ROWS = 8;
 constexpr int LB_COLS = LB_NT / LB_ROWS;  // 32
 constexpr double LB_MARGIN = 1.0 + 1e-9;
 
-template <typename WT>
-__device__ __forceinline__ double stored_weight(const char* p, int64_t i) {
-  return (double)reinterpret_cast<const WT*>(p)[i];
-}
-
-__device__ __forceinline__ double stored_at(const char* p, int wdtype, int64_t i) {
-  return wdtype == 0 ? stored_weight<uint8_t>(p, i)
-                     : (wdtype == 1 ? stored_weight<float>(p, i) : stored_weight<double>(p, i));
-}
-
 // Codebook of one image into LDS as FP64 (u, v).
 template <typename T>
 __device__ __forceinline__ void stage_codebook(const T* w, int M, double2* sw) {
@@ -69,16 +59,31 @@ struct LabelSmem {
   int32_t* cnt;   // [LB_NT / 64] per-wave candidate counts
 };
 
-// Rows r0 .. r0 + n - 1 (n <= LB_ROWS) of one image, tile by tile along the row group.
-__device__ __forceinline__ void label_rows(const char* x, int wdtype, double scale, int64_t pitch, int W, int r0,
-                                           int n, const double2* sw, int M, int32_t* lab, const LabelSmem& sm) {
+// Rows r0 .. r0 + n - 1 (n <= LB_ROWS) of one image, tile by tile along the
+// row group; each thread's weight of the next tile is loaded while the
+// current tile is labelled (pixels outside the image load at an out-of-range
+// offset, which reads 0).
+template <typename WT>
+__device__ __forceinline__ void label_rows_t(const char* x, double scale, int64_t pitch, int H, int W, int r0,
+                                             int n, const double2* sw, int M, int32_t* lab, const LabelSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tr = tid / LB_COLS, tc = tid - tr * LB_COLS;
+  const rsrc_t xr = make_rsrc(x, (uint32_t)((uint64_t)H * (uint64_t)pitch * sizeof(WT)));
+  const int r = r0 + tr;
+  const uint32_t rowoff = (uint32_t)((int64_t)r * pitch * (int64_t)sizeof(WT));
+  auto fetch = [&](int c0) {
+    const int v = c0 + tc;
+    const uint32_t bad = (uint32_t)!(tr < n && v < W) << 31;
+    return buf_load<WT>(xr, (rowoff + (uint32_t)v * (uint32_t)sizeof(WT)) | bad, 0);
+  };
+  WT wnext = fetch(0);
   for (int c0 = 0; c0 < W; c0 += LB_COLS) {
-    const int r = r0 + tr, v = c0 + tc;
+    const int v = c0 + tc;
     const bool in = tr < n && v < W;
     const int64_t e = (int64_t)r * pitch + v;
-    const bool fg = in && stored_at(x, wdtype, e) * scale > 0.0;
+    const WT wcur = wnext;
+    wnext = fetch(c0 + LB_COLS);  // past the width: reads 0, unused
+    const bool fg = in && (double)wcur * scale > 0.0;
     if (!__syncthreads_or(fg)) {  // uniform: no pixel of the tile is labelled
       if (in) lab[e] = -1;
       continue;
@@ -130,6 +135,16 @@ __device__ __forceinline__ void label_rows(const char* x, int wdtype, double sca
   }
 }
 
+__device__ __forceinline__ void label_rows(const char* x, int wdtype, double scale, int64_t pitch, int H, int W, int r0,
+                                           int n, const double2* sw, int M, int32_t* lab, const LabelSmem& sm) {
+  if (wdtype == 0)
+    label_rows_t<uint8_t>(x, scale, pitch, H, W, r0, n, sw, M, lab, sm);
+  else if (wdtype == 1)
+    label_rows_t<float>(x, scale, pitch, H, W, r0, n, sw, M, lab, sm);
+  else
+    label_rows_t<double>(x, scale, pitch, H, W, r0, n, sw, M, lab, sm);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(LB_NT) label_kernel(const char* x, int wdtype, double scale, int64_t pitch, int H,
                                                       int W, const T* w, int M, int32_t* lab) {
@@ -140,7 +155,7 @@ __global__ void __launch_bounds__(LB_NT) label_kernel(const char* x, int wdtype,
   stage_codebook(w, M, sw);
   __syncthreads();
   const int r0 = blockIdx.x * LB_ROWS;
-  label_rows(x, wdtype, scale, pitch, W, r0, min(LB_ROWS, H - r0), sw, M, lab, sm);
+  label_rows(x, wdtype, scale, pitch, H, W, r0, min(LB_ROWS, H - r0), sw, M, lab, sm);
 }
 
 __global__ void __launch_bounds__(LB_NT) label_batched_kernel(const ImageDesc* __restrict__ images,
@@ -162,7 +177,7 @@ __global__ void __launch_bounds__(LB_NT) label_batched_kernel(const ImageDesc* _
       last = t.img;
     }
     const int64_t esz = im.wdtype == 0 ? 1 : (im.wdtype == 1 ? 4 : 8);
-    label_rows(x + im.weight_off, im.wdtype, im.scale, im.pitch, im.W, t.pos, min(LB_ROWS, im.H - t.pos), sw,
+    label_rows(x + im.weight_off, im.wdtype, im.scale, im.pitch, im.H, im.W, t.pos, min(LB_ROWS, im.H - t.pos), sw,
                im.M, lab + im.weight_off / esz, sm);
   }
 }
