@@ -89,6 +89,52 @@ def test_chamfer_batched(gpu_lib):
         assert np.array_equal(got, O.chamfer_transform(cases[i].img).astype(np.float32)), i
 
 
+def ragged_batch_images():
+    """300 binary images: ragged widths around the 64-column strips, single rows and columns, all foreground,
+    all background."""
+    rng = np.random.default_rng(11)
+    imgs = [np.ones((1, 1), np.uint8), np.zeros((1, 1), np.uint8), rand_img(20, 1, 1024, 0.98),
+            rand_img(21, 60, 1024, 0.97), rand_img(22, 60, 1, 0.97), np.ones((40, 129), np.uint8),
+            np.zeros((33, 77), np.uint8), np.ones((1, 1024), np.uint8), np.ones((97, 1), np.uint8)]
+    imgs += [rand_img(30 + k, 23, w, 0.95) for k, w in enumerate((63, 64, 65, 127, 128, 129, 960, 1023))]
+    while len(imgs) < 300:
+        H, W = int(rng.integers(1, 48)), int(rng.integers(1, 1025))
+        imgs.append(rand_img(1000 + len(imgs), H, W, float(rng.uniform(0.6, 1.0))))
+    return imgs
+
+
+def test_chamfer_batched_ragged_every_image(gpu_lib):
+    """The batched transform over 300 ragged images: every image against the oracle for five masks."""
+    imgs = ragged_batch_images()
+    plan = gpu_lib.BatchPlan([torch.from_numpy(im) for im in imgs], [1] * len(imgs), [2.0] * len(imgs),
+                             [1] * len(imgs))
+    for a, b in ((3, 4), (1, 1), (1, 2), (5, 7), (64, 100)):
+        t = plan.chamfer(a, b)
+        torch.cuda.synchronize()
+        for i, im in enumerate(imgs):
+            got = plan.image(t, i).cpu().numpy()
+            assert np.array_equal(got, O.chamfer_transform(im, a, b).astype(np.float32)), (a, b, i, im.shape)
+
+
+def test_chamfer_batched_silhouettes_full(gpu_lib):
+    """All 1,400 silhouettes in one plan (the batch the benchmark times): the tallest, the widest, the smallest
+    and every 97th image equal the per-image transform bit for bit; two also against the oracle."""
+    cases = S.config3_cases(1400)
+    plan = gpu_lib.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
+                             [c.sigma for c in cases], [c.iters for c in cases])
+    t = plan.chamfer()
+    torch.cuda.synchronize()
+    shapes = [c.img.shape for c in cases]
+    pick = {int(np.argmax([h for h, _ in shapes])), int(np.argmax([w for _, w in shapes])),
+            int(np.argmin([h * w for h, w in shapes]))} | set(range(0, 1400, 97))
+    for i in sorted(pick):
+        ref = gpu_lib.chamfer(torch.from_numpy(cases[i].img).cuda())
+        assert torch.equal(plan.image(t, i), ref), i
+    for i in sorted(pick)[:2]:
+        got = plan.image(t, i).cpu().numpy()
+        assert np.array_equal(got, O.chamfer_transform(cases[i].img).astype(np.float32)), i
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_weighted_fit_config1(gpu_lib, seed):
     """Section 5: P = T(X) * G_xi with the 3-4 chamfer T; the fit on T / 3 matches the oracle."""
