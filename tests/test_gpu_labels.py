@@ -58,3 +58,35 @@ def test_batched_segments(gpu_lib):
         got = plan.image(lab, i).cpu().numpy()
         Wi = plan.unpack(w, i).cpu().double().numpy()
         assert np.array_equal(got, O.label_pixels(cases[i].img, Wi)), i
+
+
+def test_full_batch_segments(gpu_lib):
+    """All 1,400 silhouettes with their fitted codebooks (the batch the benchmark labels): every image labels
+    exactly its foreground with indices below M; the tallest, the widest, the largest codebook and every 97th
+    image equal the per-image labels bit for bit; the three smallest and a median-sized image against the
+    oracle."""
+    cases = S.config3_cases(1400)
+    plan = gpu_lib.BatchPlan([torch.from_numpy(c.img) for c in cases], [c.M for c in cases],
+                             [c.sigma for c in cases], [c.iters for c in cases])
+    w0 = plan.pack_codebooks([c.w0 for c in cases])
+    w = torch.empty_like(w0)
+    plan.run(w0, w)
+    lab = plan.label(w)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        li = plan.image(lab, i)
+        fg = torch.from_numpy(c.img).cuda() > 0
+        assert torch.equal(li >= 0, fg), i
+        assert int(li.max()) < c.M, i
+    shapes = [c.img.shape for c in cases]
+    sizes = [h * w_ for h, w_ in shapes]
+    pick = {int(np.argmax([h for h, _ in shapes])), int(np.argmax([w_ for _, w_ in shapes])),
+            int(np.argmax([c.M for c in cases]))} | set(range(0, 1400, 97))
+    for i in sorted(pick):
+        ref = gpu_lib.label(torch.from_numpy(cases[i].img).cuda(), plan.unpack(w, i))
+        assert torch.equal(plan.image(lab, i), ref), i
+    order = np.argsort(sizes, kind="stable")
+    for i in list(order[:3]) + [int(order[len(order) // 2])]:
+        got = plan.image(lab, int(i)).cpu().numpy()
+        Wi = plan.unpack(w, int(i)).cpu().double().numpy()
+        assert np.array_equal(got, O.label_pixels(cases[int(i)].img, Wi)), int(i)
